@@ -1,0 +1,166 @@
+"""Seeded synthetic inputs for the D2Q9 pseudopotential lattice update.
+
+This module generates initial density fields and parameter sets.  The tests
+feed the same arrays to the HIP library and to the CPU oracle, and the
+benchmark uses them to build its workload.  It holds none of the method's
+arithmetic: no equilibrium, force, collision or streaming, only the initial
+shapes of Sec. IV (Eqs. ISD and REL) and seeded noise.
+
+Equation of state.  A Carnahan-Starling EOS in the "a = 1, b = 4, R = 1"
+convention of Yuan and Schaefer (packing fraction b rho / 4) is Eq. CSEOS with
+a = b = c = k = 1 (UNIT_CS).  The paper's own set (Sec. IV.A) is PAPER_CS,
+whose critical point is rho_c = T_c = 1, so that its T is the reduced
+temperature.
+
+Coexistence estimates.  Initial liquid and gas densities are the Maxwell
+equal-area values (Eq. MLVDR) of UNIT_CS, tabulated below at reduced
+temperatures 0.50, 0.55, ..., 0.95 and interpolated in between (log-linear for
+the gas, linear for the liquid).  They are only starting estimates; the lattice
+relaxes to its own coexistence.
+"""
+import math
+
+import numpy as np
+
+UNIT_CS = {"eos_a": 1.0, "eos_b": 1.0, "eos_c": 1.0, "eos_k": 1.0}
+PAPER_CS = {"eos_a": 3.852462257, "eos_b": 0.1304438842, "eos_c": 2.785855166, "eos_k": 0.01}
+
+# Critical temperature and density of UNIT_CS (dP/drho = d2P/drho2 = 0).
+UNIT_CS_TC = 0.09432870313372377
+UNIT_CS_RHOC = 0.13044388419245395
+PAPER_CS_TC = 1.0
+
+# Maxwell coexistence of UNIT_CS: reduced temperature -> (rho_gas, rho_liquid).
+UNIT_CS_MAXWELL = {
+    0.50: (6.265678136210e-04, 4.540784256808e-01),
+    0.55: (1.509384291077e-03, 4.300282945352e-01),
+    0.60: (3.081458538701e-03, 4.062041397690e-01),
+    0.65: (5.586886971204e-03, 3.823354103970e-01),
+    0.70: (9.294146214955e-03, 3.581309411885e-01),
+    0.75: (1.452608460572e-02, 3.332415985387e-01),
+    0.80: (2.172324341156e-02, 3.071956823671e-01),
+    0.85: (3.158177949692e-02, 2.792620942592e-01),
+    0.90: (4.542119805617e-02, 2.480842412089e-01),
+    0.95: (6.661162921133e-02, 2.102542248280e-01),
+}
+
+# The paper's Maxwell values at T_r = 0.8 (Sec. IV.B, caption of Table DVT).
+PAPER_CS_MAXWELL = {0.80: (0.1665, 2.3550)}
+
+
+def unit_cs_coexistence(tr: float):
+    """Maxwell (rho_gas, rho_liquid) estimate of UNIT_CS at reduced temperature tr."""
+    keys = sorted(UNIT_CS_MAXWELL)
+    if not keys[0] <= tr <= keys[-1]:
+        raise ValueError(f"reduced temperature {tr} outside [{keys[0]}, {keys[-1]}]")
+    for lo, hi in zip(keys, keys[1:]):
+        if lo <= tr <= hi:
+            s = (tr - lo) / (hi - lo)
+            g0, l0 = UNIT_CS_MAXWELL[lo]
+            g1, l1 = UNIT_CS_MAXWELL[hi]
+            return math.exp((1 - s) * math.log(g0) + s * math.log(g1)), (1 - s) * l0 + s * l1
+    return UNIT_CS_MAXWELL[keys[-1]]
+
+
+def params(nx, ny, tr=0.8, tau=1.0, G=-1.0, epsilon=1.73, sigma=1.0, eos="unit",
+           force_on=True, m2_trace_alt=False):
+    """A parameter dictionary in the field names of the library's parameter block."""
+    if eos == "unit":
+        p = dict(UNIT_CS)
+        T = tr * UNIT_CS_TC
+    elif eos == "paper":
+        p = dict(PAPER_CS)
+        T = tr * PAPER_CS_TC
+    else:
+        raise ValueError(eos)
+    p.update(nx=int(nx), ny=int(ny), tau=float(tau), G=float(G), epsilon=float(epsilon),
+             sigma=float(sigma), T=float(T), force_on=bool(force_on),
+             m2_trace_alt=bool(m2_trace_alt))
+    return p
+
+
+def noise(shape, seed, amplitude=1e-3):
+    """Additive uniform noise U(-amplitude, amplitude) from NumPy's PCG64."""
+    return np.random.default_rng(seed).uniform(-amplitude, amplitude, size=shape)
+
+
+def droplet(nx, ny, radius, rho_l, rho_g, width=2.0, center=None):
+    """Circular droplet, Eq. ISD: rho = (rho_l + rho_g)/2 - (rho_l - rho_g)/2 tanh(2 (R - R0)/W),
+    with R measured from the domain centre ((nx-1)/2, (ny-1)/2) in cell units."""
+    x0, y0 = ((nx - 1) / 2.0, (ny - 1) / 2.0) if center is None else center
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    r = np.sqrt((x - x0) ** 2 + (y - y0) ** 2)
+    return 0.5 * (rho_l + rho_g) - 0.5 * (rho_l - rho_g) * np.tanh(2.0 * (r - radius) / width)
+
+
+def ellipse(nx, ny, r_max, r_min, rho_l, rho_g, width=2.0):
+    """Elliptical droplet, Eqs. ISD and REL: R0(theta) = R_min / sqrt(1 - (e cos theta)^2),
+    e = sqrt(1 - (R_min/R_max)^2), major axis along x.  theta uses atan2, which
+    leaves R0 unchanged (it depends only on cos^2 theta) and is defined at x = x0."""
+    x0, y0 = (nx - 1) / 2.0, (ny - 1) / 2.0
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    r = np.sqrt((x - x0) ** 2 + (y - y0) ** 2)
+    theta = np.arctan2(y - y0, x - x0)
+    e = math.sqrt(1.0 - (r_min / r_max) ** 2)
+    r0 = r_min / np.sqrt(1.0 - (e * np.cos(theta)) ** 2)
+    return 0.5 * (rho_l + rho_g) - 0.5 * (rho_l - rho_g) * np.tanh(2.0 * (r - r0) / width)
+
+
+def slab(nx, ny, rho_l, rho_g, width=2.0):
+    """Flat liquid slab in the middle half of the domain, uniform in y:
+    rho = rho_g + (rho_l - rho_g)/2 [tanh(2 (x - x1)/W) - tanh(2 (x - x2)/W)],
+    x1 = nx/4 - 1/2, x2 = 3 nx/4 - 1/2."""
+    x = np.arange(nx, dtype=np.float64)
+    x1, x2 = nx / 4.0 - 0.5, 3.0 * nx / 4.0 - 0.5
+    row = rho_g + 0.5 * (rho_l - rho_g) * (np.tanh(2.0 * (x - x1) / width)
+                                          - np.tanh(2.0 * (x - x2) / width))
+    return np.ascontiguousarray(np.broadcast_to(row, (ny, nx)))
+
+
+def smooth_random(nx, ny, seed, mean, amplitude, modes=4):
+    """A smooth periodic random field: a few low Fourier modes with seeded phases.
+    Used for single-step parity on fields without interfaces."""
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    out = np.full((ny, nx), float(mean))
+    for _ in range(modes):
+        kx, ky = rng.integers(0, 3, size=2)
+        if kx == 0 and ky == 0:
+            kx = 1
+        ph = rng.uniform(0, 2 * np.pi)
+        a = rng.uniform(0.3, 1.0)
+        out += amplitude * a / modes * np.cos(2 * np.pi * (kx * x / nx + ky * y / ny) + ph)
+    return out
+
+
+# ---- named workloads (sizes and recipes of the synthetic configurations) ----
+
+def droplet_64(seed=1):
+    """64 x 64 periodic droplet, R0 = 16, W = 2, T_r = 0.8, tau = 1, UNIT_CS,
+    Maxwell densities, U(+-1e-3) noise.  Returns (params, rho0)."""
+    p = params(64, 64, tr=0.8, tau=1.0)
+    rg, rl = unit_cs_coexistence(0.8)
+    rho0 = droplet(64, 64, 16.0, rl, rg, 2.0) + noise((64, 64), seed)
+    return p, rho0
+
+
+def slab_case(n=2048, ny=None, tr=0.8, seed=None, tau=1.0):
+    """n x ny periodic flat slab (middle half liquid), W = 2, UNIT_CS at reduced
+    temperature tr, Maxwell densities, U(+-1e-3) noise.  The default seeds are
+    2, 3, 4, 5 for T_r = 0.6, 0.7, 0.8, 0.9.  Returns (params, rho0)."""
+    ny = n if ny is None else ny
+    if seed is None:
+        seed = {0.6: 2, 0.7: 3, 0.8: 4, 0.9: 5}.get(round(tr, 2), 2)
+    p = params(n, ny, tr=tr, tau=tau)
+    rg, rl = unit_cs_coexistence(tr)
+    rho0 = slab(n, ny, rl, rg, 2.0) + noise((ny, n), seed)
+    return p, rho0
+
+
+def ellipse_case(n=1024, tr=0.7, tau=1.0, seed=8, r_max=160.0, r_min=120.0):
+    """n x n periodic elliptical droplet (semi-axes r_max along x, r_min along y),
+    W = 2, UNIT_CS at reduced temperature tr, U(+-1e-3) noise."""
+    p = params(n, n, tr=tr, tau=tau)
+    rg, rl = unit_cs_coexistence(tr)
+    rho0 = ellipse(n, n, r_max, r_min, rl, rg, 2.0) + noise((n, n), seed)
+    return p, rho0
