@@ -1,0 +1,168 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 force-approach pseudopotential
+ * lattice Boltzmann library.
+ *
+ * The method is that of Czelusniak, Mapelli, Guzella, Cabezas-Gomez and
+ * Wagner, "Force approach for the pseudopotential lattice Boltzmann method"
+ * (arXiv:2003.07968).  One time step (lbm_step) is, for every cell x of a
+ * periodic nx * ny lattice:
+ *
+ *   1. streaming in pull form, f_i(x, t) = f*_i(x - c_i, t - 1)       (Eq. TLBE)
+ *   2. density rho = sum_i f_i                                        (Eq. FD)
+ *   3. pressure from the Carnahan-Starling EOS                        (Eq. CSEOS)
+ *      P = k [c rho T (1 + b rho + (b rho)^2 - (b rho)^3)/(1 - b rho)^3 - a rho^2]
+ *      and pseudopotential psi = sqrt((P - cs^2 rho)/G)                (Eq. DED)
+ *   4. moments of w_i psi(x + c_i)                          (Eqs. FOMED, SOMED)
+ *   5. the interaction force                                          (Eq. IFT)
+ *      F = F^SC - (3/4) eps cs^2 G F^(1) + (sigma - 1) cs^2 G F^(2)
+ *      with F^SC of Eq. SCF and F^(1), F^(2) of Eqs. DFTCCC, DFTCST
+ *   6. velocity rho u = sum_i f_i c_i + F/2                           (Eq. FMD)
+ *   7. BGK collision with the Guo source                (Eqs. BGKCO, GFS, GFSBGK)
+ *      f*_i = f_i - (f_i - f_i^eq)/tau + (1 - 1/(2 tau)) w_i [c_i.F/cs^2
+ *             + (c_ia c_ib - cs^2 d_ab) F_a u_b / cs^4],  f^eq of Eq. SEDF
+ *
+ * with the D2Q9 velocities and weights of Sec. II.A (Eq. VelocitySet),
+ * cs^2 = 1/3, in FP64.
+ *
+ * Conventions.
+ *   - Every function is extern "C", returns an lbm_status (0 = LBM_OK) or a
+ *     plain value, and never throws.
+ *   - Pointers named d_* are HIP device pointers; everything else is host.
+ *   - Fields are row-major [ny][nx], x fastest: cell (x, y) is y*nx + x.
+ *   - Populations exchanged through the ABI are [9][ny][nx] in the order of
+ *     Eq. VelocitySet (0 rest; 1..4 = +x, +y, -x, -y; 5..8 = (+,+), (-,+),
+ *     (-,-), (+,-)) and hold f(t), the post-streaming, pre-collision state.
+ *     The library's internal storage layout is private.
+ *   - Ownership: the caller allocates and frees the device workspace and all
+ *     device arrays; the library owns only the host-side handle.
+ *   - Streams: all device work is enqueued, in order, on the HIP stream given
+ *     to lbm_init (NULL = the null stream).  Calls on one handle must not
+ *     overlap from several host threads.
+ *   - Errors: bad arguments are rejected synchronously with
+ *     LBM_ERR_INVALID_ARG and change nothing.  A density leaving the EOS domain
+ *     (rho <= 0, b rho >= 1, (P - cs^2 rho)/G < 0 or non-finite) is recorded
+ *     on the device in a sticky error word (first step, then lowest cell index);
+ *     lbm_sync, lbm_moments and lbm_diagnostics then return LBM_ERR_DOMAIN and
+ *     lbm_last_error names the step and cell.  The library never clamps psi.
+ *     After a domain error the populations are undefined.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_INVALID_ARG = -1, /* rejected argument; nothing was changed        */
+    LBM_ERR_DOMAIN = -2,      /* sticky: EOS domain left at some step and cell */
+    LBM_ERR_DEVICE = -3,      /* a HIP call failed                              */
+    LBM_ERR_OOM = -4,         /* host allocation failed                         */
+    LBM_ERR_STATE = -5        /* handle not usable for this call                */
+} lbm_status;
+
+typedef enum {
+    LBM_STORE_F64 = 0 /* populations stored in FP64 */
+} lbm_storage;
+
+/* Physical and numerical parameters, named as in the paper. */
+typedef struct {
+    int32_t nx, ny;   /* periodic lattice, each >= 3                               */
+    double tau;       /* BGK relaxation time, > 0.5 (Eq. BGKCO)                    */
+    double G;         /* nonzero; sign and scale of Eq. DED.  The force depends
+                         only on its sign (psi scales as |G|^-1/2).               */
+    double epsilon;   /* coexistence parameter of Eq. IFT (paper: 1.73)            */
+    double sigma;     /* surface-tension parameter of Eq. IFT (paper: 1/8 .. 4)    */
+    double eos_a, eos_b, eos_c, eos_k; /* Eq. CSEOS constants                      */
+    double T;         /* absolute temperature of Eq. CSEOS                         */
+    int32_t force_on; /* 0: F = 0, plain BGK; 1: the force of Eq. IFT              */
+    int32_t m2_trace_alt; /* 0: M2_bb as the trace of Eq. SOMED; 1: the
+                             alternative 2 cs^2 (M0 - psi) stated after Eq. DFTCST */
+    int32_t storage;  /* lbm_storage; only LBM_STORE_F64                           */
+    double rho_ref;   /* reference density for shifted storage; unused for F64     */
+} lbm_params;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Bytes of device workspace lbm_init needs for these parameters (0 if they are
+ * invalid).  The workspace holds two population copies (2 * 9 * nx * ny
+ * doubles), a density snapshot for the steady-state criterion and a few KB of
+ * reduction scratch and error word. */
+size_t lbm_workspace_bytes(const lbm_params *params);
+
+/* Validate params, carve the workspace (device memory of at least
+ * lbm_workspace_bytes, 256-byte aligned, owned by the caller and kept alive
+ * until lbm_destroy) and set t = 0 with f(0) = f^eq(rho0, u0) (Sec. IV.A,
+ * below Eq. ISD).  d_rho0 is [ny][nx]; d_ux0 and d_uy0 may be NULL (zero
+ * velocity).  hip_stream is a hipStream_t.  On success *out receives a new
+ * handle.  The initial density must lie in the EOS domain; that is checked
+ * by the first step or moments call, not here. */
+lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspace_bytes,
+                    const double *d_rho0, const double *d_ux0, const double *d_uy0,
+                    void *hip_stream, lbm_handle **out);
+
+/* Enqueue nsteps >= 0 time steps (asynchronous).  Returns LBM_ERR_DEVICE if a
+ * launch fails; domain errors surface at lbm_sync. */
+lbm_status lbm_step(lbm_handle *h, int64_t nsteps);
+
+/* Wait for the handle's stream and return the sticky status. */
+lbm_status lbm_sync(lbm_handle *h);
+
+/* Macroscopic fields at the current time t: rho (Eq. FD), u (Eq. FMD), the
+ * force F (Eq. IFT, zero when force_on = 0) and psi (Eq. DED, zero when
+ * force_on = 0).  Each output is a device array [ny][nx] or NULL to skip it.
+ * Synchronous: returns after the fields are written, with the sticky status. */
+lbm_status lbm_moments(lbm_handle *h, double *d_rho, double *d_ux, double *d_uy, double *d_Fx,
+                       double *d_Fy, double *d_psi);
+
+/* Global diagnostics at time t into host out[6]:
+ *   out[0] mass, sum rho
+ *   out[1], out[2] momentum, sum rho u_x and sum rho u_y (= sum f c + F/2)
+ *   out[3] sum |rho(t) - rho_snap|, out[4] sum |rho(t)|: the numerator and
+ *          denominator of the steady-state criterion (Eq. SSC), where rho_snap
+ *          is the density at the previous lbm_diagnostics call (or at t = 0)
+ *   out[5] max |u|
+ * The call then replaces rho_snap by rho(t).  Sums are reduced in a fixed
+ * order (deterministic for a given lattice size).  Synchronous. */
+lbm_status lbm_diagnostics(lbm_handle *h, double out[6]);
+
+/* Copy f(t) out to d_f ([9][ny][nx] FP64, device).  Synchronous. */
+lbm_status lbm_get_populations(lbm_handle *h, double *d_f);
+
+/* Replace the state by f(t) = d_f ([9][ny][nx] FP64, device) and set the
+ * time counter to t >= 0 (checkpoint restart).  Synchronous.  Clears nothing
+ * else: a sticky error stays. */
+lbm_status lbm_set_populations(lbm_handle *h, const double *d_f, int64_t t);
+
+/* Number of completed steps. */
+int64_t lbm_time(const lbm_handle *h);
+
+/* Override the launch shape of the sweep kernels: block_x threads per
+ * workgroup (a multiple of 64 in [64, 512]; each workgroup owns block_x - 2
+ * columns) and seg_rows rows walked by each workgroup (>= 1).  0 keeps the
+ * library's choice.  Every shape gives bitwise-identical populations. */
+lbm_status lbm_set_launch(lbm_handle *h, int32_t block_x, int32_t seg_rows);
+
+/* The launch shape in use: out[0] = block_x, out[1] = seg_rows,
+ * out[2] = workgroups per step. */
+lbm_status lbm_get_launch(const lbm_handle *h, int32_t out[3]);
+
+const char *lbm_status_string(lbm_status s);
+
+/* Text of the last error on this handle ("" if none).  Valid until the next
+ * call on the handle. */
+const char *lbm_last_error(const lbm_handle *h);
+
+/* Free the host handle.  The workspace stays the caller's; the stream is not
+ * synchronised. */
+void lbm_destroy(lbm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

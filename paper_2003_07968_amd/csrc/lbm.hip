@@ -1,0 +1,869 @@
+// lbm.hip -- D2Q9 force-approach pseudopotential lattice Boltzmann update for
+// AMD CDNA4 (gfx950), behind the C ABI of include/lbm.h.
+//
+// Method: Czelusniak et al., arXiv:2003.07968.  Per cell and step: pull
+// streaming (Eq. TLBE), density (Eq. FD), Carnahan-Starling pressure
+// (Eq. CSEOS), pseudopotential (Eq. DED), psi moments (Eqs. FOMED, SOMED), the
+// proposed force (Eq. IFT), velocity (Eq. FMD) and the Guo-forced BGK
+// collision (Eqs. BGKCO, SEDF, GFS, GFSBGK).  Everything is FP64.
+//
+// Kernel design (one fused pass per step, HBM-bound):
+//   * populations are structure-of-arrays planes X_i[y][x] holding the
+//     post-collision values of the previous step; the pulled value is
+//     f_i(x) = X_i(x - c_i), so every plane row is read with unit stride
+//     (shifted by at most one element) and written with unit stride;
+//   * a workgroup of BX threads owns a strip of BX - 2 interior columns plus
+//     one halo column on each side, and walks a segment of rows.  At each row
+//     it loads the pulled populations of the row ahead, turns them into rho
+//     and psi, exchanges psi with its x-neighbours through one double-buffered
+//     LDS row, and keeps the 3x3 psi window of its own column in registers;
+//     populations are prefetched one further row ahead.  Each population is
+//     read from HBM once per step, apart from the two halo columns per strip
+//     and the two halo rows per segment, which are re-read through L2;
+//   * workgroups are numbered so that consecutive tiles of the lattice (the
+//     strips of a row band) land on the same XCD and share its L2, and
+//     neighbouring segments walk in opposite directions, so both workgroups of
+//     a segment boundary touch its rows at about the same time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm.h"
+
+namespace {
+
+constexpr int kQ = 9;
+constexpr int kXcds = 8;          // MI355X: workgroups are dealt round-robin to 8 XCDs
+constexpr int kMaxTiles = 1 << 15; // bound on workgroups per sweep (sizes the scratch)
+constexpr int kDiag = 6;          // diagnostics values per workgroup
+constexpr size_t kAlign = 256;
+
+// Coefficients of one lattice, precomputed on the host.
+struct Coeffs {
+    int nx, ny;
+    size_t plane;   // elements per population plane (row stride is nx)
+    double omega;   // 1/tau
+    double guo;     // 1 - 1/(2 tau), Eq. GFSBGK
+    double eos_b;   // b of Eq. CSEOS
+    double kcT;     // k c T
+    double ka;      // k a
+    double invG;    // 1/G
+    // Eq. IFT with cs^2 = 1/3 substituted:
+    //   F_a = cSC psi0 M1_a + cA (M1_b M2_ab) + cB M1_a M2_bb
+    // cSC = -2G/cs^2 = -6G; cA = (3/2 eps - (sigma - 1)) cs^2 G / cs^6
+    // = 9G (1.5 eps - sigma + 1); cB = (sigma - 1) cs^2 G / cs^6 = 9G (sigma - 1).
+    double cSC, cA, cB;
+    int force_on;
+    int trace_alt;
+};
+
+// Tile decomposition of one sweep.
+struct Tiles {
+    int nstrips, nseg, ntiles, per_xcd;
+};
+
+// Optional outputs of the moments sweep.
+struct Fields {
+    double *rho, *ux, *uy, *Fx, *Fy, *psi;
+};
+
+enum Mode { kStep = 0, kMoments = 1, kDiagnostics = 2 };
+
+__device__ __forceinline__ int wrap_lo(int v, int n) { return v < 0 ? v + n : v; }
+__device__ __forceinline__ int wrap_hi(int v, int n) { return v >= n ? v - n : v; }
+
+// Pulled populations of row r at column x: f_i(x, r) = X_i(x - c_ix, r - c_iy).
+__device__ __forceinline__ void load_pulled(const double *__restrict__ src, const Coeffs &c,
+                                            int r, int x, int xm, int xp, double f[kQ])
+{
+    const int rm = wrap_lo(r - 1, c.ny), rp = wrap_hi(r + 1, c.ny);
+    const size_t P = c.plane;
+    const double *row_r = src + (size_t)r * c.nx;
+    const double *row_m = src + (size_t)rm * c.nx;
+    const double *row_p = src + (size_t)rp * c.nx;
+    f[0] = row_r[x];
+    f[1] = row_r[1 * P + xm];
+    f[2] = row_m[2 * P + x];
+    f[3] = row_r[3 * P + xp];
+    f[4] = row_p[4 * P + x];
+    f[5] = row_m[5 * P + xm];
+    f[6] = row_m[6 * P + xp];
+    f[7] = row_p[7 * P + xp];
+    f[8] = row_p[8 * P + xm];
+}
+
+// Density (Eq. FD) and pseudopotential (Eqs. CSEOS, DED).  Returns false when
+// the density is outside the EOS domain.
+__device__ __forceinline__ bool rho_psi(const double f[kQ], const Coeffs &c, double &rho,
+                                        double &psi)
+{
+    rho = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
+    if (!c.force_on) {
+        psi = 0.0;
+        return rho > 0.0 && rho < INFINITY;
+    }
+    const double br = c.eos_b * rho;
+    const double num = 1.0 + br * (1.0 + br * (1.0 - br));
+    const double om = 1.0 - br;
+    const double P = c.kcT * rho * num / (om * om * om) - c.ka * rho * rho;
+    const double rad = (P - rho * (1.0 / 3.0)) * c.invG;
+    psi = sqrt(rad);
+    return rho > 0.0 && br < 1.0 && rad >= 0.0 && rad < INFINITY;
+}
+
+__device__ __forceinline__ void flag_domain(unsigned long long *err, long long t, int r, int x,
+                                            int nx)
+{
+    const unsigned long long key =
+        ((unsigned long long)t << 32) | (unsigned long long)((size_t)r * nx + x);
+    atomicMin(err, key);
+}
+
+// Force of Eq. IFT from psi_i = psi(x + c_i) (Eqs. FOMED, SOMED, SCF,
+// DFTCCC, DFTCST).
+__device__ __forceinline__ void force(const double s[kQ], const Coeffs &c, double &Fx,
+                                      double &Fy)
+{
+    const double d13 = s[1] - s[3], d24 = s[2] - s[4];
+    const double s13 = s[1] + s[3], s24 = s[2] + s[4];
+    const double a58 = s[5] - s[7], b68 = s[6] - s[8];
+    const double s58 = (s[5] + s[6]) + (s[7] + s[8]);
+    const double M1x = d13 * (1.0 / 9.0) + (a58 - b68) * (1.0 / 36.0);
+    const double M1y = d24 * (1.0 / 9.0) + (a58 + b68) * (1.0 / 36.0);
+    const double M2xx = s[0] * (-4.0 / 27.0) + s13 * (2.0 / 27.0) - s24 * (1.0 / 27.0) +
+                        s58 * (1.0 / 54.0);
+    const double M2yy = s[0] * (-4.0 / 27.0) - s13 * (1.0 / 27.0) + s24 * (2.0 / 27.0) +
+                        s58 * (1.0 / 54.0);
+    const double M2xy = ((s[5] + s[7]) - (s[6] + s[8])) * (1.0 / 36.0);
+    double tr;
+    if (c.trace_alt) {
+        const double M0 = s[0] * (4.0 / 9.0) + (s13 + s24) * (1.0 / 9.0) + s58 * (1.0 / 36.0);
+        tr = (2.0 / 3.0) * (M0 - s[0]);
+    } else {
+        tr = M2xx + M2yy;
+    }
+    Fx = c.cSC * s[0] * M1x + c.cA * (M1x * M2xx + M1y * M2xy) + c.cB * M1x * tr;
+    Fy = c.cSC * s[0] * M1y + c.cA * (M1x * M2xy + M1y * M2yy) + c.cB * M1y * tr;
+}
+
+// Velocity (Eq. FMD).
+__device__ __forceinline__ void velocity(const double f[kQ], double rho, double Fx, double Fy,
+                                         double &ux, double &uy)
+{
+    const double jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+    const double jy = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
+    const double inv = 1.0 / rho;
+    ux = (jx + 0.5 * Fx) * inv;
+    uy = (jy + 0.5 * Fy) * inv;
+}
+
+// BGK collision with the Guo source (Eqs. BGKCO, SEDF, GFS, GFSBGK), in place.
+__device__ __forceinline__ void collide(double f[kQ], double rho, double ux, double uy,
+                                        double Fx, double Fy, const Coeffs &c)
+{
+    const double usq = ux * ux + uy * uy;
+    const double uF = ux * Fx + uy * Fy;
+    const double base = 1.0 - 1.5 * usq;      // f^eq bracket without the c.u terms
+    const double sbase = -3.0 * uF;           // S bracket without the c.F terms
+    const double om = c.omega, g = c.guo;
+    const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
+    // rest population
+    {
+        const double feq = w0 * rho * base;
+        const double S = g * w0 * sbase;
+        f[0] = f[0] - om * (f[0] - feq) + S;
+    }
+    // moving populations: c_i.u and c_i.F for each direction
+    const double cu[8] = {ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
+    const double cF[8] = {Fx, Fy, -Fx, -Fy, Fx + Fy, Fy - Fx, -Fx - Fy, Fx - Fy};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double w = k < 4 ? w1 : w2;
+        const double feq = w * rho * (base + cu[k] * (3.0 + 4.5 * cu[k]));
+        const double S = g * w * (sbase + cF[k] * (3.0 + 9.0 * cu[k]));
+        f[k + 1] = f[k + 1] - om * (f[k + 1] - feq) + S;
+    }
+}
+
+// Equilibrium (Eq. SEDF) of direction i.
+__device__ __forceinline__ double feq_dir(int i, double rho, double ux, double uy)
+{
+    const int cx[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int cy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    const double cu = cx[i] * ux + cy[i] * uy;
+    return w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
+}
+
+template <int BX>
+__device__ __forceinline__ double warp_or_block_sum(double v, double *lds_red)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    constexpr int W = BX / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds_red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        s += lds_red[k];
+    return s;
+}
+
+template <int BX>
+__device__ __forceinline__ double warp_or_block_max(double v, double *lds_red)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, 64));
+    constexpr int W = BX / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds_red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        s = fmax(s, lds_red[k]);
+    return s;
+}
+
+// The 3x3 psi window of the current column: own column (o), x-1 (l) and x+1
+// (r) at the trailing (T), current (C) and leading (L) rows.
+struct Window {
+    double oT, oC, oL, lT, lC, lL, rT, rC, rL;
+};
+
+// psi(x + c_i) for the current row when the walk goes in direction DIR
+// (+1: the leading row is y + 1; -1: it is y - 1).
+template <int DIR>
+__device__ __forceinline__ void window_to_stencil(const Window &w, double s[kQ])
+{
+    const double oU = DIR > 0 ? w.oL : w.oT, oD = DIR > 0 ? w.oT : w.oL;
+    const double lU = DIR > 0 ? w.lL : w.lT, lD = DIR > 0 ? w.lT : w.lL;
+    const double rU = DIR > 0 ? w.rL : w.rT, rD = DIR > 0 ? w.rT : w.rL;
+    s[0] = w.oC;
+    s[1] = w.rC;
+    s[2] = oU;
+    s[3] = w.lC;
+    s[4] = oD;
+    s[5] = rU;
+    s[6] = lU;
+    s[7] = lD;
+    s[8] = rD;
+}
+
+template <int BX, int MODE, int DIR>
+__device__ __forceinline__ void walk(const double *__restrict__ src, double *__restrict__ dst,
+                                     const Coeffs &c, long long t,
+                                     unsigned long long *__restrict__ err, const Fields &fo,
+                                     double *__restrict__ rho_snap, int ys, int ye, int x,
+                                     int xm, int xp, bool active, bool interior, double *lds,
+                                     double acc[kDiag])
+{
+    const int tx = threadIdx.x;
+    const int nrows = ye - ys;
+    int y = DIR > 0 ? ys : ye - 1;
+
+    Window w;
+    double fC[kQ], fL[kQ], fN[kQ];
+    double rhoC = 1.0, rhoL = 1.0;
+    bool ok = true;
+
+    // prologue: psi of the trailing and current rows, populations of the
+    // current and leading rows
+    {
+        double ft[kQ], rho_t;
+        const int rt = DIR > 0 ? wrap_lo(y - 1, c.ny) : wrap_hi(y + 1, c.ny);
+        w.oT = 0.0;
+        w.oC = 0.0;
+        if (active) {
+            load_pulled(src, c, rt, x, xm, xp, ft);
+            load_pulled(src, c, y, x, xm, xp, fC);
+            if (!rho_psi(ft, c, rho_t, w.oT)) flag_domain(err, t, rt, x, c.nx);
+            if (!rho_psi(fC, c, rhoC, w.oC)) flag_domain(err, t, y, x, c.nx);
+            const int rl = DIR > 0 ? wrap_hi(y + 1, c.ny) : wrap_lo(y - 1, c.ny);
+            load_pulled(src, c, rl, x, xm, xp, fL);
+        }
+        lds[tx] = w.oT;
+        lds[BX + tx] = w.oC;
+        __syncthreads();
+        if (interior) {
+            w.lT = lds[tx - 1];
+            w.rT = lds[tx + 1];
+            w.lC = lds[BX + tx - 1];
+            w.rC = lds[BX + tx + 1];
+        }
+        __syncthreads();
+    }
+
+    for (int k = 0; k < nrows; ++k, y += DIR) {
+        // prefetch the populations of the row after the leading one
+        if (active && k + 1 < nrows) {
+            int rn = y + 2 * DIR;
+            rn = DIR > 0 ? wrap_hi(rn, c.ny) : wrap_lo(rn, c.ny);
+            load_pulled(src, c, rn, x, xm, xp, fN);
+        }
+        // psi of the leading row, shared with the x-neighbours
+        w.oL = 0.0;
+        if (active) {
+            if (!rho_psi(fL, c, rhoL, w.oL)) {
+                const int rl = DIR > 0 ? wrap_hi(y + 1, c.ny) : wrap_lo(y - 1, c.ny);
+                flag_domain(err, t, rl, x, c.nx);
+            }
+        }
+        double *buf = lds + (k & 1) * BX;
+        buf[tx] = w.oL;
+        __syncthreads();
+        if (interior) {
+            w.lL = buf[tx - 1];
+            w.rL = buf[tx + 1];
+
+            double Fx = 0.0, Fy = 0.0;
+            if (c.force_on) {
+                double s[kQ];
+                window_to_stencil<DIR>(w, s);
+                force(s, c, Fx, Fy);
+            }
+            double ux, uy;
+            velocity(fC, rhoC, Fx, Fy, ux, uy);
+            const size_t cell = (size_t)y * c.nx + x;
+            if (MODE == kStep) {
+                collide(fC, rhoC, ux, uy, Fx, Fy, c);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i)
+                    dst[i * c.plane + cell] = fC[i];
+            } else if (MODE == kMoments) {
+                if (fo.rho) fo.rho[cell] = rhoC;
+                if (fo.ux) fo.ux[cell] = ux;
+                if (fo.uy) fo.uy[cell] = uy;
+                if (fo.Fx) fo.Fx[cell] = Fx;
+                if (fo.Fy) fo.Fy[cell] = Fy;
+                if (fo.psi) fo.psi[cell] = w.oC;
+            } else {
+                const double prev = rho_snap[cell];
+                rho_snap[cell] = rhoC;
+                acc[0] += rhoC;
+                acc[1] += rhoC * ux;
+                acc[2] += rhoC * uy;
+                acc[3] += fabs(rhoC - prev);
+                acc[4] += fabs(rhoC);
+                acc[5] = fmax(acc[5], sqrt(ux * ux + uy * uy));
+            }
+        }
+        // rotate the window and the population registers
+        w.oT = w.oC; w.lT = w.lC; w.rT = w.rC;
+        w.oC = w.oL; w.lC = w.lL; w.rC = w.rL;
+        rhoC = rhoL;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            fC[i] = fL[i];
+            fL[i] = fN[i];
+        }
+    }
+    (void)ok;
+}
+
+template <int BX, int MODE>
+__global__ __launch_bounds__(BX) void sweep_kernel(const double *__restrict__ src,
+                                                   double *__restrict__ dst, Coeffs c, Tiles tl,
+                                                   long long t,
+                                                   unsigned long long *__restrict__ err,
+                                                   Fields fo, double *__restrict__ rho_snap,
+                                                   double *__restrict__ partials)
+{
+    __shared__ double lds[2 * BX];
+    // XCD-aware tile order: workgroup b runs on XCD b % 8, and each XCD takes
+    // a contiguous run of tiles (strips of consecutive row bands).
+    const int b = blockIdx.x;
+    const int tile = (b % kXcds) * tl.per_xcd + b / kXcds;
+    if (tile >= tl.ntiles) return;  // uniform for the whole workgroup
+    const int seg = tile / tl.nstrips;
+    const int strip = tile - seg * tl.nstrips;
+    const int xs = (int)((long long)strip * c.nx / tl.nstrips);
+    const int xe = (int)((long long)(strip + 1) * c.nx / tl.nstrips);
+    const int ys = (int)((long long)seg * c.ny / tl.nseg);
+    const int ye = (int)((long long)(seg + 1) * c.ny / tl.nseg);
+
+    const int tx = threadIdx.x;
+    const int width = xe - xs;                 // interior columns, <= BX - 2
+    const bool active = tx <= width + 1;
+    const bool interior = tx >= 1 && tx <= width;
+    int x = xs - 1 + (active ? tx : 1);
+    x = wrap_hi(wrap_lo(x, c.nx), c.nx);
+    const int xm = wrap_lo(x - 1, c.nx), xp = wrap_hi(x + 1, c.nx);
+
+    double acc[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (seg & 1)
+        walk<BX, MODE, -1>(src, dst, c, t, err, fo, rho_snap, ys, ye, x, xm, xp, active,
+                           interior, lds, acc);
+    else
+        walk<BX, MODE, +1>(src, dst, c, t, err, fo, rho_snap, ys, ye, x, xm, xp, active,
+                           interior, lds, acc);
+
+    if (MODE == kDiagnostics) {
+        __shared__ double red[BX / 64];
+        double out[kDiag];
+#pragma unroll
+        for (int j = 0; j < kDiag - 1; ++j)
+            out[j] = warp_or_block_sum<BX>(acc[j], red);
+        out[kDiag - 1] = warp_or_block_max<BX>(acc[kDiag - 1], red);
+        if (tx == 0) {
+#pragma unroll
+            for (int j = 0; j < kDiag; ++j)
+                partials[(size_t)tile * kDiag + j] = out[j];
+        }
+    }
+}
+
+// Second stage of the diagnostics: one workgroup sums the per-tile partials
+// in a fixed order.
+__global__ __launch_bounds__(256) void reduce_partials(const double *__restrict__ partials,
+                                                        int ntiles, double *__restrict__ out)
+{
+    __shared__ double red[4];
+    double acc[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < ntiles; k += 256) {
+#pragma unroll
+        for (int j = 0; j < kDiag - 1; ++j)
+            acc[j] += partials[(size_t)k * kDiag + j];
+        acc[kDiag - 1] = fmax(acc[kDiag - 1], partials[(size_t)k * kDiag + kDiag - 1]);
+    }
+    double res[kDiag];
+#pragma unroll
+    for (int j = 0; j < kDiag - 1; ++j)
+        res[j] = warp_or_block_sum<256>(acc[j], red);
+    res[kDiag - 1] = warp_or_block_max<256>(acc[kDiag - 1], red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < kDiag; ++j)
+            out[j] = res[j];
+    }
+}
+
+// Initial state f(0) = f^eq(rho0, u0) in pull storage: X_i(z) = f_i^eq at z + c_i.
+__global__ __launch_bounds__(256) void init_kernel(double *__restrict__ X, Coeffs c,
+                                                    const double *__restrict__ rho0,
+                                                    const double *__restrict__ ux0,
+                                                    const double *__restrict__ uy0)
+{
+    const size_t n = (size_t)c.nx * c.ny;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int x = (int)(k % c.nx), y = (int)(k / c.nx);
+    const int cx[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int cy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int xx = wrap_hi(wrap_lo(x + cx[i], c.nx), c.nx);
+        const int yy = wrap_hi(wrap_lo(y + cy[i], c.ny), c.ny);
+        const size_t s = (size_t)yy * c.nx + xx;
+        X[i * c.plane + k] =
+            feq_dir(i, rho0[s], ux0 ? ux0[s] : 0.0, uy0 ? uy0[s] : 0.0);
+    }
+}
+
+// Canonical f(t) <-> pull storage.  to_canonical: f_i(x) = X_i(x - c_i);
+// otherwise X_i(z) = f_i(z + c_i).
+__global__ __launch_bounds__(256) void permute_kernel(const double *__restrict__ in,
+                                                       double *__restrict__ out, Coeffs c,
+                                                       int to_canonical)
+{
+    const size_t n = (size_t)c.nx * c.ny;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int x = (int)(k % c.nx), y = (int)(k / c.nx);
+    const int cx[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int cy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const int sgn = to_canonical ? -1 : 1;
+    const size_t in_plane = to_canonical ? c.plane : n;
+    const size_t out_plane = to_canonical ? n : c.plane;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int xx = wrap_hi(wrap_lo(x + sgn * cx[i], c.nx), c.nx);
+        const int yy = wrap_hi(wrap_lo(y + sgn * cy[i], c.ny), c.ny);
+        out[i * out_plane + k] = in[i * in_plane + (size_t)yy * c.nx + xx];
+    }
+}
+
+__global__ void fill_u64(unsigned long long *p, unsigned long long v) { *p = v; }
+
+__global__ void copy_plane(const double *__restrict__ a, double *__restrict__ b, size_t n)
+{
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) b[k] = a[k];
+}
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct lbm_handle {
+    lbm_params p;
+    Coeffs c;
+    hipStream_t stream;
+    double *cur, *nxt;       // population buffers (pull storage)
+    double *rho_snap;        // density snapshot for Eq. SSC
+    double *partials;        // per-tile diagnostics
+    double *diag_out;        // kDiag doubles
+    unsigned long long *err; // sticky domain-error key
+    int64_t t;
+    int bx, seg_rows;
+    Tiles tiles;
+    lbm_status sticky;
+    std::string last_error;
+};
+
+namespace {
+
+struct Layout {
+    size_t err, diag_out, partials, rho_snap, bufA, bufB, total, plane;
+};
+
+Layout layout_for(const lbm_params *p)
+{
+    Layout L;
+    const size_t n = (size_t)p->nx * p->ny;
+    L.plane = round_up(n, kAlign / sizeof(double));
+    size_t off = 0;
+    L.err = off;
+    off += kAlign;
+    L.diag_out = off;
+    off += kAlign;
+    L.partials = off;
+    off += round_up((size_t)kMaxTiles * kDiag * sizeof(double), kAlign);
+    L.rho_snap = off;
+    off += L.plane * sizeof(double);
+    L.bufA = off;
+    off += kQ * L.plane * sizeof(double);
+    L.bufB = off;
+    off += kQ * L.plane * sizeof(double);
+    L.total = off;
+    return L;
+}
+
+bool params_valid(const lbm_params *p, std::string *why)
+{
+    auto fail = [&](const char *m) {
+        if (why) *why = m;
+        return false;
+    };
+    if (!p) return fail("params is NULL");
+    if (p->nx < 3 || p->ny < 3) return fail("nx and ny must be >= 3");
+    if ((double)p->nx * (double)p->ny >= 4294967296.0) return fail("nx*ny must be < 2^32");
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail("tau must be > 0.5");
+    if (!(p->G != 0.0) || !std::isfinite(p->G)) return fail("G must be nonzero and finite");
+    if (!std::isfinite(p->epsilon) || !std::isfinite(p->sigma)) return fail("eps/sigma not finite");
+    if (!std::isfinite(p->eos_a) || !std::isfinite(p->eos_b) || !std::isfinite(p->eos_c) ||
+        !std::isfinite(p->eos_k) || !std::isfinite(p->T))
+        return fail("EOS constants not finite");
+    if (p->force_on != 0 && p->force_on != 1) return fail("force_on must be 0 or 1");
+    if (p->m2_trace_alt != 0 && p->m2_trace_alt != 1) return fail("m2_trace_alt must be 0 or 1");
+    if (p->storage != LBM_STORE_F64) return fail("unsupported storage mode");
+    return true;
+}
+
+Coeffs make_coeffs(const lbm_params *p, size_t plane)
+{
+    Coeffs c;
+    c.nx = p->nx;
+    c.ny = p->ny;
+    c.plane = plane;
+    c.omega = 1.0 / p->tau;
+    c.guo = 1.0 - 1.0 / (2.0 * p->tau);
+    c.eos_b = p->eos_b;
+    c.kcT = p->eos_k * p->eos_c * p->T;
+    c.ka = p->eos_k * p->eos_a;
+    c.invG = 1.0 / p->G;
+    c.cSC = -6.0 * p->G;
+    c.cA = 9.0 * p->G * (1.5 * p->epsilon - p->sigma + 1.0);
+    c.cB = 9.0 * p->G * (p->sigma - 1.0);
+    c.force_on = p->force_on;
+    c.trace_alt = p->m2_trace_alt;
+    return c;
+}
+
+bool make_tiles(int nx, int ny, int bx, int seg_rows, Tiles *tl)
+{
+    const int w = bx - 2;
+    tl->nstrips = (nx + w - 1) / w;
+    tl->nseg = (ny + seg_rows - 1) / seg_rows;
+    const long long nt = (long long)tl->nstrips * tl->nseg;
+    if (nt > kMaxTiles) return false;
+    tl->ntiles = (int)nt;
+    tl->per_xcd = (tl->ntiles + kXcds - 1) / kXcds;
+    return true;
+}
+
+// Default launch shape: the workgroup width that wastes the fewest lanes on
+// ragged strips (ties to the wider one up to 256 threads), then enough row
+// segments for about 8 waves per CU on 256 CUs, each segment at least 8 rows.
+void default_launch(int nx, int ny, int *bx_out, int *rows_out)
+{
+    int best = 256;
+    double best_eff = -1.0;
+    for (int bx = 64; bx <= 512; bx += 64) {
+        const int nstrips = (nx + bx - 3) / (bx - 2);
+        const double eff = (double)nx / ((double)nstrips * bx);
+        const double score = eff - (bx > 256 ? 0.02 : 0.0);
+        if (score > best_eff + 1e-12) {
+            best_eff = score;
+            best = bx;
+        }
+    }
+    const int nstrips = (nx + best - 3) / (best - 2);
+    const double target_waves = 256.0 * 8.0;
+    int nseg = (int)std::ceil(target_waves / ((double)nstrips * (best / 64)));
+    nseg = std::max(1, std::min(nseg, ny));
+    int rows = (ny + nseg - 1) / nseg;
+    rows = std::max(rows, std::min(8, ny));
+    while ((long long)nstrips * ((ny + rows - 1) / rows) > kMaxTiles)
+        ++rows;
+    *bx_out = best;
+    *rows_out = rows;
+}
+
+lbm_status dev_fail(lbm_handle *h, hipError_t e, const char *what)
+{
+    if (h) {
+        h->last_error = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return LBM_ERR_DEVICE;
+}
+
+template <int MODE>
+hipError_t launch_sweep(lbm_handle *h, const double *src, double *dst, Fields fo)
+{
+    const dim3 grid((unsigned)(h->tiles.per_xcd * kXcds));
+    const Coeffs &c = h->c;
+    switch (h->bx) {
+#define LBM_CASE(BX)                                                                          \
+    case BX:                                                                                  \
+        hipLaunchKernelGGL((sweep_kernel<BX, MODE>), grid, dim3(BX), 0, h->stream, src, dst, c, \
+                           h->tiles, (long long)h->t, h->err, fo, h->rho_snap, h->partials); \
+        break;
+        LBM_CASE(64)
+        LBM_CASE(128)
+        LBM_CASE(192)
+        LBM_CASE(256)
+        LBM_CASE(320)
+        LBM_CASE(384)
+        LBM_CASE(448)
+        LBM_CASE(512)
+#undef LBM_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+lbm_status read_sticky(lbm_handle *h)
+{
+    unsigned long long key = ~0ull;
+    hipError_t e = hipMemcpyAsync(&key, h->err, sizeof(key), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return dev_fail(h, e, "reading the error word");
+    if (key != ~0ull) {
+        const long long step = (long long)(key >> 32);
+        const long long cell = (long long)(key & 0xffffffffull);
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "EOS domain left at step %lld, cell %lld (x=%lld, y=%lld)", step, cell,
+                      cell % h->p.nx, cell / h->p.nx);
+        h->last_error = buf;
+        h->sticky = LBM_ERR_DOMAIN;
+    }
+    return h->sticky;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params *params)
+{
+    if (!params_valid(params, nullptr)) return 0;
+    return layout_for(params).total;
+}
+
+lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspace_bytes,
+                    const double *d_rho0, const double *d_ux0, const double *d_uy0,
+                    void *hip_stream, lbm_handle **out)
+{
+    if (!out) return LBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!params_valid(params, nullptr)) return LBM_ERR_INVALID_ARG;
+    const Layout L = layout_for(params);
+    if (!d_workspace || workspace_bytes < L.total || !d_rho0) return LBM_ERR_INVALID_ARG;
+    if (((uintptr_t)d_workspace) % kAlign != 0) return LBM_ERR_INVALID_ARG;
+
+    lbm_handle *h = new (std::nothrow) lbm_handle();
+    if (!h) return LBM_ERR_OOM;
+    h->p = *params;
+    h->c = make_coeffs(params, L.plane);
+    h->stream = (hipStream_t)hip_stream;
+    char *ws = (char *)d_workspace;
+    h->err = (unsigned long long *)(ws + L.err);
+    h->diag_out = (double *)(ws + L.diag_out);
+    h->partials = (double *)(ws + L.partials);
+    h->rho_snap = (double *)(ws + L.rho_snap);
+    h->cur = (double *)(ws + L.bufA);
+    h->nxt = (double *)(ws + L.bufB);
+    h->t = 0;
+    h->sticky = LBM_OK;
+    default_launch(params->nx, params->ny, &h->bx, &h->seg_rows);
+    if (!make_tiles(params->nx, params->ny, h->bx, h->seg_rows, &h->tiles)) {
+        delete h;
+        return LBM_ERR_INVALID_ARG;
+    }
+
+    const size_t n = (size_t)params->nx * params->ny;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(fill_u64, dim3(1), dim3(1), 0, h->stream, h->err, ~0ull);
+    hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, h->stream, h->cur, h->c, d_rho0,
+                       d_ux0, d_uy0);
+    hipLaunchKernelGGL(copy_plane, dim3(blocks), dim3(256), 0, h->stream, d_rho0, h->rho_snap, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete h;
+        return LBM_ERR_DEVICE;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_handle *h, int64_t nsteps)
+{
+    if (!h) return LBM_ERR_INVALID_ARG;
+    if (nsteps < 0) {
+        h->last_error = "nsteps must be >= 0";
+        return LBM_ERR_INVALID_ARG;
+    }
+    for (int64_t k = 0; k < nsteps; ++k) {
+        hipError_t e = launch_sweep<kStep>(h, h->cur, h->nxt, Fields{});
+        if (e != hipSuccess) return dev_fail(h, e, "launching the step kernel");
+        std::swap(h->cur, h->nxt);
+        ++h->t;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_handle *h)
+{
+    if (!h) return LBM_ERR_INVALID_ARG;
+    return read_sticky(h);
+}
+
+lbm_status lbm_moments(lbm_handle *h, double *d_rho, double *d_ux, double *d_uy, double *d_Fx,
+                       double *d_Fy, double *d_psi)
+{
+    if (!h) return LBM_ERR_INVALID_ARG;
+    Fields fo{d_rho, d_ux, d_uy, d_Fx, d_Fy, d_psi};
+    hipError_t e = launch_sweep<kMoments>(h, h->cur, nullptr, fo);
+    if (e != hipSuccess) return dev_fail(h, e, "launching the moments kernel");
+    return read_sticky(h);
+}
+
+lbm_status lbm_diagnostics(lbm_handle *h, double out[6])
+{
+    if (!h || !out) return LBM_ERR_INVALID_ARG;
+    hipError_t e = launch_sweep<kDiagnostics>(h, h->cur, nullptr, Fields{});
+    if (e != hipSuccess) return dev_fail(h, e, "launching the diagnostics kernel");
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, h->stream, h->partials,
+                       h->tiles.ntiles, h->diag_out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return dev_fail(h, e, "launching the reduction kernel");
+    e = hipMemcpyAsync(out, h->diag_out, kDiag * sizeof(double), hipMemcpyDeviceToHost,
+                       h->stream);
+    if (e != hipSuccess) return dev_fail(h, e, "copying diagnostics");
+    return read_sticky(h);
+}
+
+lbm_status lbm_get_populations(lbm_handle *h, double *d_f)
+{
+    if (!h || !d_f) return LBM_ERR_INVALID_ARG;
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
+                       h->cur, d_f, h->c, 1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return dev_fail(h, e, "copying populations out");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_handle *h, const double *d_f, int64_t t)
+{
+    if (!h || !d_f || t < 0) return LBM_ERR_INVALID_ARG;
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
+                       d_f, h->cur, h->c, 0);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return dev_fail(h, e, "copying populations in");
+    h->t = t;
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_handle *h) { return h ? h->t : -1; }
+
+lbm_status lbm_set_launch(lbm_handle *h, int32_t block_x, int32_t seg_rows)
+{
+    if (!h) return LBM_ERR_INVALID_ARG;
+    int bx = h->bx, rows = h->seg_rows;
+    int dbx, drows;
+    default_launch(h->p.nx, h->p.ny, &dbx, &drows);
+    if (block_x != 0) bx = block_x;
+    else bx = dbx;
+    if (seg_rows != 0) rows = seg_rows;
+    else rows = drows;
+    if (bx < 64 || bx > 512 || bx % 64 != 0 || rows < 1) {
+        h->last_error = "block_x must be a multiple of 64 in [64, 512] and seg_rows >= 1";
+        return LBM_ERR_INVALID_ARG;
+    }
+    Tiles tl;
+    if (!make_tiles(h->p.nx, h->p.ny, bx, rows, &tl)) {
+        h->last_error = "launch shape needs too many workgroups";
+        return LBM_ERR_INVALID_ARG;
+    }
+    h->bx = bx;
+    h->seg_rows = rows;
+    h->tiles = tl;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_launch(const lbm_handle *h, int32_t out[3])
+{
+    if (!h || !out) return LBM_ERR_INVALID_ARG;
+    out[0] = h->bx;
+    out[1] = h->seg_rows;
+    out[2] = h->tiles.per_xcd * kXcds;
+    return LBM_OK;
+}
+
+const char *lbm_status_string(lbm_status s)
+{
+    switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_INVALID_ARG: return "invalid argument";
+    case LBM_ERR_DOMAIN: return "EOS domain error";
+    case LBM_ERR_DEVICE: return "device error";
+    case LBM_ERR_OOM: return "out of host memory";
+    case LBM_ERR_STATE: return "invalid handle state";
+    }
+    return "unknown status";
+}
+
+const char *lbm_last_error(const lbm_handle *h) { return h ? h->last_error.c_str() : ""; }
+
+void lbm_destroy(lbm_handle *h) { delete h; }
+
+}  // extern "C"

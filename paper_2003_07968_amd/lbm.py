@@ -1,0 +1,264 @@
+"""Python binding of the C ABI in include/lbm.h (liblbm.so, HIP for gfx950).
+
+The functions below carry the C names and only marshal arguments: every step
+of the lattice update runs in the library's HIP kernels.  PyTorch provides
+device memory and the stream.  The library must have been built
+(`python -m paper_2003_07968_amd.build`); loading fails loudly otherwise, and
+there is no CPU fallback.
+
+Arrays: fields are torch.float64 CUDA tensors of shape (ny, nx), populations
+(9, ny, nx), contiguous, on the device of the stream.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK = 0
+LBM_ERR_INVALID_ARG = -1
+LBM_ERR_DOMAIN = -2
+LBM_ERR_DEVICE = -3
+LBM_ERR_OOM = -4
+LBM_ERR_STATE = -5
+LBM_STORE_F64 = 0
+
+_ALIGN = 256
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("G", ctypes.c_double),
+        ("epsilon", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("eos_a", ctypes.c_double), ("eos_b", ctypes.c_double),
+        ("eos_c", ctypes.c_double), ("eos_k", ctypes.c_double), ("T", ctypes.c_double),
+        ("force_on", ctypes.c_int32), ("m2_trace_alt", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("rho_ref", ctypes.c_double),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, message=""):
+        self.status = status
+        text = _load().lbm_status_string(status).decode()
+        super().__init__(f"{text}: {message}" if message else text)
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing; build it with `python -m paper_2003_07968_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(lbm_params)
+        H = ctypes.c_void_p
+        lib.lbm_workspace_bytes.argtypes = [P]
+        lib.lbm_workspace_bytes.restype = ctypes.c_size_t
+        lib.lbm_init.argtypes = [P, _VP, ctypes.c_size_t, _VP, _VP, _VP, _VP,
+                                 ctypes.POINTER(H)]
+        lib.lbm_init.restype = ctypes.c_int
+        lib.lbm_step.argtypes = [H, ctypes.c_int64]
+        lib.lbm_step.restype = ctypes.c_int
+        lib.lbm_sync.argtypes = [H]
+        lib.lbm_sync.restype = ctypes.c_int
+        lib.lbm_moments.argtypes = [H] + [_VP] * 6
+        lib.lbm_moments.restype = ctypes.c_int
+        lib.lbm_diagnostics.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
+        lib.lbm_diagnostics.restype = ctypes.c_int
+        lib.lbm_get_populations.argtypes = [H, _VP]
+        lib.lbm_get_populations.restype = ctypes.c_int
+        lib.lbm_set_populations.argtypes = [H, _VP, ctypes.c_int64]
+        lib.lbm_set_populations.restype = ctypes.c_int
+        lib.lbm_time.argtypes = [H]
+        lib.lbm_time.restype = ctypes.c_int64
+        lib.lbm_set_launch.argtypes = [H, ctypes.c_int32, ctypes.c_int32]
+        lib.lbm_set_launch.restype = ctypes.c_int
+        lib.lbm_get_launch.argtypes = [H, ctypes.POINTER(ctypes.c_int32)]
+        lib.lbm_get_launch.restype = ctypes.c_int
+        lib.lbm_status_string.argtypes = [ctypes.c_int]
+        lib.lbm_status_string.restype = ctypes.c_char_p
+        lib.lbm_last_error.argtypes = [H]
+        lib.lbm_last_error.restype = ctypes.c_char_p
+        lib.lbm_destroy.argtypes = [H]
+        lib.lbm_destroy.restype = None
+        _lib = lib
+    return _lib
+
+
+EXPORTED = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_sync", "lbm_moments",
+            "lbm_diagnostics", "lbm_get_populations", "lbm_set_populations", "lbm_time",
+            "lbm_set_launch", "lbm_get_launch", "lbm_status_string", "lbm_last_error",
+            "lbm_destroy")
+
+
+def make_params(p: dict) -> lbm_params:
+    """lbm_params from a dictionary with the struct's field names."""
+    return lbm_params(int(p["nx"]), int(p["ny"]), float(p["tau"]), float(p["G"]),
+                      float(p["epsilon"]), float(p["sigma"]), float(p["eos_a"]),
+                      float(p["eos_b"]), float(p["eos_c"]), float(p["eos_k"]), float(p["T"]),
+                      int(bool(p.get("force_on", True))), int(bool(p.get("m2_trace_alt", False))),
+                      int(p.get("storage", LBM_STORE_F64)), float(p.get("rho_ref", 0.0)))
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---- the C functions, one to one ----
+
+def lbm_workspace_bytes(params: lbm_params) -> int:
+    return _load().lbm_workspace_bytes(ctypes.byref(params))
+
+
+def lbm_init(params, workspace, rho0, ux0=None, uy0=None, stream=None):
+    """Returns a handle (an opaque integer)."""
+    lib = _load()
+    h = ctypes.c_void_p()
+    ws_ptr = workspace.data_ptr()
+    ws_bytes = workspace.numel() * workspace.element_size()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib.lbm_init(ctypes.byref(params), ctypes.c_void_p(ws_ptr), ws_bytes, _dev_ptr(rho0),
+                      _dev_ptr(ux0), _dev_ptr(uy0), ctypes.c_void_p(s.cuda_stream),
+                      ctypes.byref(h))
+    if st != LBM_OK:
+        raise LbmError(st)
+    return h.value
+
+
+def _check(h, st):
+    if st != LBM_OK:
+        raise LbmError(st, _load().lbm_last_error(h).decode())
+
+
+def lbm_step(h, nsteps):
+    _check(h, _load().lbm_step(h, int(nsteps)))
+
+
+def lbm_sync(h):
+    return _load().lbm_sync(h)
+
+
+def lbm_moments(h, rho=None, ux=None, uy=None, Fx=None, Fy=None, psi=None):
+    _check(h, _load().lbm_moments(h, *[_dev_ptr(t) for t in (rho, ux, uy, Fx, Fy, psi)]))
+
+
+def lbm_diagnostics(h):
+    out = (ctypes.c_double * 6)()
+    _check(h, _load().lbm_diagnostics(h, out))
+    return list(out)
+
+
+def lbm_get_populations(h, f):
+    _check(h, _load().lbm_get_populations(h, _dev_ptr(f)))
+
+
+def lbm_set_populations(h, f, t):
+    _check(h, _load().lbm_set_populations(h, _dev_ptr(f), int(t)))
+
+
+def lbm_time(h):
+    return _load().lbm_time(h)
+
+
+def lbm_set_launch(h, block_x=0, seg_rows=0):
+    _check(h, _load().lbm_set_launch(h, int(block_x), int(seg_rows)))
+
+
+def lbm_get_launch(h):
+    out = (ctypes.c_int32 * 3)()
+    _check(h, _load().lbm_get_launch(h, out))
+    return tuple(out)
+
+
+def lbm_last_error(h):
+    return _load().lbm_last_error(h).decode()
+
+
+def lbm_destroy(h):
+    _load().lbm_destroy(h)
+
+
+# ---- convenience wrapper owning its torch workspace ----
+
+class Lattice:
+    """One periodic lattice on the current CUDA device and stream."""
+
+    def __init__(self, p: dict, rho0, ux0=None, uy0=None, device="cuda", stream=None):
+        self.params = make_params(p)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        nbytes = lbm_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise LbmError(LBM_ERR_INVALID_ARG, "parameters rejected")
+        # torch's caching allocator hands out 512-byte aligned blocks
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        assert self.workspace.data_ptr() % _ALIGN == 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+
+        def dev(a):
+            if a is None:
+                return None
+            t = torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+            return t
+        self._rho0, self._ux0, self._uy0 = dev(rho0), dev(ux0), dev(uy0)
+        self.handle = lbm_init(self.params, self.workspace, self._rho0, self._ux0, self._uy0,
+                               self.stream)
+
+    def step(self, n=1):
+        lbm_step(self.handle, n)
+
+    def sync(self):
+        st = lbm_sync(self.handle)
+        if st != LBM_OK:
+            raise LbmError(st, lbm_last_error(self.handle))
+
+    @property
+    def t(self):
+        return lbm_time(self.handle)
+
+    def moments(self):
+        shape = (self.ny, self.nx)
+        out = {k: torch.empty(shape, dtype=torch.float64, device=self.workspace.device)
+               for k in ("rho", "ux", "uy", "Fx", "Fy", "psi")}
+        lbm_moments(self.handle, **out)
+        return out
+
+    def diagnostics(self):
+        v = lbm_diagnostics(self.handle)
+        return dict(zip(["mass", "mom_x", "mom_y", "ssc_num", "ssc_den", "umax"], v))
+
+    def populations(self):
+        f = torch.empty((9, self.ny, self.nx), dtype=torch.float64, device=self.workspace.device)
+        lbm_get_populations(self.handle, f)
+        return f
+
+    def set_populations(self, f, t):
+        lbm_set_populations(self.handle, f.contiguous(), t)
+
+    def set_launch(self, block_x=0, seg_rows=0):
+        lbm_set_launch(self.handle, block_x, seg_rows)
+
+    def launch(self):
+        return lbm_get_launch(self.handle)
+
+    def close(self):
+        if self.handle:
+            lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,67 @@
+"""The C-ABI library loads on the CPU host and exports every function that
+include/lbm.h declares; host-only entry points validate their arguments.
+No device work is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2003_07968_amd import lbm
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_2003_07968_amd import build
+        build.build()
+    return lbm._load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lbm_init", "lbm_step", "lbm_moments", "lbm_sync", "lbm_diagnostics",
+                     "lbm_get_populations", "lbm_set_populations", "lbm_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2003_07968_amd import lbm
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(lbm.EXPORTED)
+
+
+def test_workspace_size_and_validation(lib):
+    from paper_2003_07968_amd import lbm
+    from paper_2003_07968_amd import workloads as W
+    p = lbm.make_params(W.params(64, 48, tr=0.8))
+    n = lib.lbm_workspace_bytes(ctypes.byref(p))
+    # two population copies of 9 planes, one density snapshot, small scratch
+    assert n >= (2 * 9 + 1) * 64 * 48 * 8
+    assert n < (2 * 9 + 1) * 64 * 48 * 8 + 4 * 2**20
+    for field, value in (("tau", 0.5), ("G", 0.0), ("nx", 2), ("storage", 5), ("force_on", 2)):
+        q = lbm.make_params(W.params(64, 48, tr=0.8))
+        setattr(q, field, value)
+        assert lib.lbm_workspace_bytes(ctypes.byref(q)) == 0, field
+    h = ctypes.c_void_p()
+    st = lib.lbm_init(ctypes.byref(p), None, 0, None, None, None, None, ctypes.byref(h))
+    assert st == lbm.LBM_ERR_INVALID_ARG and not h.value
+
+
+def test_status_strings(lib):
+    from paper_2003_07968_amd import lbm
+    for st in (lbm.LBM_OK, lbm.LBM_ERR_INVALID_ARG, lbm.LBM_ERR_DOMAIN, lbm.LBM_ERR_DEVICE,
+               lbm.LBM_ERR_OOM, lbm.LBM_ERR_STATE):
+        assert lib.lbm_status_string(st)
+    assert lib.lbm_last_error(None) == b""
+    assert lib.lbm_time(None) == -1
