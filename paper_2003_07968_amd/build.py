@@ -16,6 +16,9 @@ INCLUDE = os.path.join(ROOT, "include")
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+    # no implicit multiply-add contraction: the kernels spell their fma()s out,
+    # so results do not depend on how the compiler schedules inlined copies
+    "-ffp-contract=off",
     # packed FP32 instructions stay disabled in all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{INCLUDE}",

@@ -33,21 +33,27 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
+#include <utility>
 
 #include "lbm.h"
 
 namespace {
 
 constexpr int kQ = 9;
-constexpr int kXcds = 8;          // MI355X: workgroups are dealt round-robin to 8 XCDs
 constexpr int kMaxTiles = 1 << 15; // bound on workgroups per sweep (sizes the scratch)
 constexpr int kDiag = 6;          // diagnostics values per workgroup
+#ifndef LBM_PREFETCH
+#define LBM_PREFETCH 1
+#endif
+constexpr int kPrefetch = LBM_PREFETCH; // rows in flight beyond the leading row (step sweep)
 constexpr size_t kAlign = 256;
 
 // Coefficients of one lattice, precomputed on the host.
 struct Coeffs {
     int nx, ny;
-    size_t plane;   // elements per population plane (row stride is nx)
+    int pitch;      // row stride of a population plane, in elements (>= nx)
+    size_t plane;   // stride between population planes, in elements
     double omega;   // 1/tau
     double guo;     // 1 - 1/(2 tau), Eq. GFSBGK
     double eos_b;   // b of Eq. CSEOS
@@ -63,9 +69,12 @@ struct Coeffs {
     int trace_alt;
 };
 
-// Tile decomposition of one sweep.
+// Tile decomposition of one sweep.  Strip s covers interior columns
+// [s * width, min(nx, (s + 1) * width)); width is a multiple of 16 columns
+// (128 bytes) whenever the lattice needs more than one strip, so that the
+// stores of neighbouring workgroups never share a cache line.
 struct Tiles {
-    int nstrips, nseg, ntiles, per_xcd;
+    int nstrips, nseg, ntiles, width;
 };
 
 // Optional outputs of the moments sweep.
@@ -79,50 +88,63 @@ __device__ __forceinline__ int wrap_lo(int v, int n) { return v < 0 ? v + n : v;
 __device__ __forceinline__ int wrap_hi(int v, int n) { return v >= n ? v - n : v; }
 
 // Pulled populations of row r at column x: f_i(x, r) = X_i(x - c_ix, r - c_iy).
+// Row bases are uniform across the workgroup (scalar registers) and the
+// column enters as a 32-bit byte offset, so each load is a single
+// scalar-base + vector-offset global load.
+struct Cols {
+    uint32_t o, m, p;  // byte offsets of columns x, x - 1 (wrapped), x + 1 (wrapped)
+};
+
+__device__ __forceinline__ double ld(const double *__restrict__ row, uint32_t byte_off)
+{
+    return *(const double *)((const char *)row + byte_off);
+}
+
 __device__ __forceinline__ void load_pulled(const double *__restrict__ src, const Coeffs &c,
-                                            int r, int x, int xm, int xp, double f[kQ])
+                                            int r, const Cols &x, double f[kQ])
 {
     const int rm = wrap_lo(r - 1, c.ny), rp = wrap_hi(r + 1, c.ny);
     const size_t P = c.plane;
-    const double *row_r = src + (size_t)r * c.nx;
-    const double *row_m = src + (size_t)rm * c.nx;
-    const double *row_p = src + (size_t)rp * c.nx;
-    f[0] = row_r[x];
-    f[1] = row_r[1 * P + xm];
-    f[2] = row_m[2 * P + x];
-    f[3] = row_r[3 * P + xp];
-    f[4] = row_p[4 * P + x];
-    f[5] = row_m[5 * P + xm];
-    f[6] = row_m[6 * P + xp];
-    f[7] = row_p[7 * P + xp];
-    f[8] = row_p[8 * P + xm];
+    const double *row_r = src + (size_t)r * c.pitch;
+    const double *row_m = src + (size_t)rm * c.pitch;
+    const double *row_p = src + (size_t)rp * c.pitch;
+    f[0] = ld(row_r, x.o);
+    f[1] = ld(row_r + 1 * P, x.m);
+    f[2] = ld(row_m + 2 * P, x.o);
+    f[3] = ld(row_r + 3 * P, x.p);
+    f[4] = ld(row_p + 4 * P, x.o);
+    f[5] = ld(row_m + 5 * P, x.m);
+    f[6] = ld(row_m + 6 * P, x.p);
+    f[7] = ld(row_p + 7 * P, x.p);
+    f[8] = ld(row_p + 8 * P, x.m);
 }
 
 // Density (Eq. FD) and pseudopotential (Eqs. CSEOS, DED).  Returns false when
-// the density is outside the EOS domain.
+// the density is outside the EOS domain (with FORCE = 0, when it is not
+// positive and finite).
+template <int FORCE>
 __device__ __forceinline__ bool rho_psi(const double f[kQ], const Coeffs &c, double &rho,
                                         double &psi)
 {
     rho = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
-    if (!c.force_on) {
+    if (!FORCE) {
         psi = 0.0;
         return rho > 0.0 && rho < INFINITY;
     }
     const double br = c.eos_b * rho;
-    const double num = 1.0 + br * (1.0 + br * (1.0 - br));
+    const double num = fma(br, fma(br, 1.0 - br, 1.0), 1.0);  // 1 + br + br^2 - br^3
     const double om = 1.0 - br;
-    const double P = c.kcT * rho * num / (om * om * om) - c.ka * rho * rho;
-    const double rad = (P - rho * (1.0 / 3.0)) * c.invG;
+    const double P = fma(c.kcT * rho, num / (om * om * om), -c.ka * rho * rho);
+    const double rad = fma(rho, -1.0 / 3.0, P) * c.invG;
     psi = sqrt(rad);
     return rho > 0.0 && br < 1.0 && rad >= 0.0 && rad < INFINITY;
 }
 
-__device__ __forceinline__ void flag_domain(unsigned long long *err, long long t, int r, int x,
-                                            int nx)
+// Error key of a cell: steps first, then the cell index, so that the
+// smallest key is the first failure in the order the oracle reports it.
+__device__ __forceinline__ unsigned long long domain_key(long long t, int r, int x, int nx)
 {
-    const unsigned long long key =
-        ((unsigned long long)t << 32) | (unsigned long long)((size_t)r * nx + x);
-    atomicMin(err, key);
+    return ((unsigned long long)t << 32) | (unsigned long long)((size_t)r * nx + x);
 }
 
 // Force of Eq. IFT from psi_i = psi(x + c_i) (Eqs. FOMED, SOMED, SCF,
@@ -141,15 +163,13 @@ __device__ __forceinline__ void force(const double s[kQ], const Coeffs &c, doubl
     const double M2yy = s[0] * (-4.0 / 27.0) - s13 * (1.0 / 27.0) + s24 * (2.0 / 27.0) +
                         s58 * (1.0 / 54.0);
     const double M2xy = ((s[5] + s[7]) - (s[6] + s[8])) * (1.0 / 36.0);
-    double tr;
-    if (c.trace_alt) {
-        const double M0 = s[0] * (4.0 / 9.0) + (s13 + s24) * (1.0 / 9.0) + s58 * (1.0 / 36.0);
-        tr = (2.0 / 3.0) * (M0 - s[0]);
-    } else {
-        tr = M2xx + M2yy;
-    }
-    Fx = c.cSC * s[0] * M1x + c.cA * (M1x * M2xx + M1y * M2xy) + c.cB * M1x * tr;
-    Fy = c.cSC * s[0] * M1y + c.cA * (M1x * M2xy + M1y * M2yy) + c.cB * M1y * tr;
+    const double M0 = s[0] * (4.0 / 9.0) + (s13 + s24) * (1.0 / 9.0) + s58 * (1.0 / 36.0);
+    const double tr = c.trace_alt ? (2.0 / 3.0) * (M0 - s[0]) : M2xx + M2yy;
+    const double ax = fma(M1x, M2xx, M1y * M2xy);  // (M1 . M2)_x
+    const double ay = fma(M1x, M2xy, M1y * M2yy);  // (M1 . M2)_y
+    const double sc = c.cSC * s[0], tb = c.cB * tr;
+    Fx = fma(sc, M1x, fma(c.cA, ax, tb * M1x));
+    Fy = fma(sc, M1y, fma(c.cA, ay, tb * M1y));
 }
 
 // Velocity (Eq. FMD).
@@ -163,31 +183,35 @@ __device__ __forceinline__ void velocity(const double f[kQ], double rho, double 
     uy = (jy + 0.5 * Fy) * inv;
 }
 
-// BGK collision with the Guo source (Eqs. BGKCO, SEDF, GFS, GFSBGK), in place.
+// BGK collision with the Guo source (Eqs. BGKCO, SEDF, GFS, GFSBGK), in place:
+//   f^eq_i = w_i rho (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+//   S_i    = (1 - 1/(2 tau)) w_i (3 c.F + 9 (c.F)(c.u) - 3 u.F)
+//   f_i   <- f_i + (f^eq_i - f_i)/tau + S_i
+// Multiply-adds are written as explicit fma(); the file is compiled without
+// implicit contraction, so every inlined copy rounds the same way.
 __device__ __forceinline__ void collide(double f[kQ], double rho, double ux, double uy,
                                         double Fx, double Fy, const Coeffs &c)
 {
-    const double usq = ux * ux + uy * uy;
-    const double uF = ux * Fx + uy * Fy;
-    const double base = 1.0 - 1.5 * usq;      // f^eq bracket without the c.u terms
+    const double usq = fma(ux, ux, uy * uy);
+    const double uF = fma(ux, Fx, uy * Fy);
+    const double base = fma(-1.5, usq, 1.0);  // f^eq bracket without the c.u terms
     const double sbase = -3.0 * uF;           // S bracket without the c.F terms
     const double om = c.omega, g = c.guo;
-    const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
-    // rest population
+    const double wr0 = (4.0 / 9.0) * rho, wr1 = (1.0 / 9.0) * rho, wr2 = (1.0 / 36.0) * rho;
+    const double gw0 = g * (4.0 / 9.0), gw1 = g * (1.0 / 9.0), gw2 = g * (1.0 / 36.0);
     {
-        const double feq = w0 * rho * base;
-        const double S = g * w0 * sbase;
-        f[0] = f[0] - om * (f[0] - feq) + S;
+        const double feq = wr0 * base;
+        const double S = gw0 * sbase;
+        f[0] = fma(om, feq - f[0], f[0]) + S;
     }
-    // moving populations: c_i.u and c_i.F for each direction
     const double cu[8] = {ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
     const double cF[8] = {Fx, Fy, -Fx, -Fy, Fx + Fy, Fy - Fx, -Fx - Fy, Fx - Fy};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const double w = k < 4 ? w1 : w2;
-        const double feq = w * rho * (base + cu[k] * (3.0 + 4.5 * cu[k]));
-        const double S = g * w * (sbase + cF[k] * (3.0 + 9.0 * cu[k]));
-        f[k + 1] = f[k + 1] - om * (f[k + 1] - feq) + S;
+        const double wr = k < 4 ? wr1 : wr2, gw = k < 4 ? gw1 : gw2;
+        const double feq = wr * fma(cu[k], fma(4.5, cu[k], 3.0), base);
+        const double S = gw * fma(cF[k], fma(9.0, cu[k], 3.0), sbase);
+        f[k + 1] = fma(om, feq - f[k + 1], f[k + 1]) + S;
     }
 }
 
@@ -237,143 +261,168 @@ __device__ __forceinline__ double warp_or_block_max(double v, double *lds_red)
     return s;
 }
 
-// The 3x3 psi window of the current column: own column (o), x-1 (l) and x+1
-// (r) at the trailing (T), current (C) and leading (L) rows.
-struct Window {
-    double oT, oC, oL, lT, lC, lL, rT, rC, rL;
+// psi (own column o, x - 1 in l, x + 1 in r) and rho (own column) of one row.
+struct Row {
+    double l, o, r, rho;
 };
 
-// psi(x + c_i) for the current row when the walk goes in direction DIR
-// (+1: the leading row is y + 1; -1: it is y - 1).
+// psi(x + c_i) for the current row C when the walk goes in direction DIR
+// (+1: the leading row L is y + 1 and the trailing row T is y - 1; -1: the
+// other way round).
 template <int DIR>
-__device__ __forceinline__ void window_to_stencil(const Window &w, double s[kQ])
+__device__ __forceinline__ void stencil(const Row &T, const Row &C, const Row &L, double s[kQ])
 {
-    const double oU = DIR > 0 ? w.oL : w.oT, oD = DIR > 0 ? w.oT : w.oL;
-    const double lU = DIR > 0 ? w.lL : w.lT, lD = DIR > 0 ? w.lT : w.lL;
-    const double rU = DIR > 0 ? w.rL : w.rT, rD = DIR > 0 ? w.rT : w.rL;
-    s[0] = w.oC;
-    s[1] = w.rC;
-    s[2] = oU;
-    s[3] = w.lC;
-    s[4] = oD;
-    s[5] = rU;
-    s[6] = lU;
-    s[7] = lD;
-    s[8] = rD;
+    const Row &U = DIR > 0 ? L : T;  // row y + 1
+    const Row &D = DIR > 0 ? T : L;  // row y - 1
+    s[0] = C.o;
+    s[1] = C.r;
+    s[2] = U.o;
+    s[3] = C.l;
+    s[4] = D.o;
+    s[5] = U.r;
+    s[6] = U.l;
+    s[7] = D.l;
+    s[8] = D.r;
 }
 
-template <int BX, int MODE, int DIR>
-__device__ __forceinline__ void walk(const double *__restrict__ src, double *__restrict__ dst,
-                                     const Coeffs &c, long long t,
-                                     unsigned long long *__restrict__ err, const Fields &fo,
-                                     double *__restrict__ rho_snap, int ys, int ye, int x,
-                                     int xm, int xp, bool active, bool interior, double *lds,
-                                     double acc[kDiag])
+// Calls f(integral_constant<int, J>) for J = 0 .. N-1, fully unrolled.
+template <class F, int... J>
+__device__ __forceinline__ void unroll(F &&f, std::integer_sequence<int, J...>)
 {
+    (f(std::integral_constant<int, J>{}), ...);
+}
+
+// One workgroup walks rows [ys, ye) of its strip in direction DIR, with the
+// populations of PF rows beyond the leading row in flight.  K = PF + 2
+// population register sets and K psi rows rotate through their roles; the
+// loop is unrolled K times so that the rotation is register renaming.
+//   row k (0-based within the segment) is output row y0 + k DIR;
+//   at iteration k: populations of row k are in set k % K (collided),
+//   of row k + 1 in set (k + 1) % K (turned into the leading psi row), and
+//   row k + 1 + PF is loaded into set (k + 1 + PF) % K;
+//   psi rows k - 1, k, k + 1 are in rows (k) % K, (k + 1) % K, (k + 2) % K.
+// The row body is straight-line code: every lane loads (lanes outside the
+// strip read a valid column, rows past the segment end are clamped to its
+// halo row) and computes; only the stores are masked.  Without branches
+// around the loads the compiler's wait counters stay exact, so a prefetch
+// really stays in flight while the current row is computed.  Domain
+// failures are folded into a per-lane minimum key and published once.
+template <int BX, int MODE, int DIR, int PF, int FORCE>
+__device__ __forceinline__ void walk(const double *__restrict__ src, double *__restrict__ dst,
+                                     const Coeffs &c, long long t, const Fields &fo,
+                                     double *__restrict__ rho_snap, int ys, int ye, int x,
+                                     const Cols &cols, bool active, bool interior, double *lds,
+                                     double acc[kDiag], unsigned long long &bad)
+{
+    constexpr int K = PF + 2;
     const int tx = threadIdx.x;
+    const int txm = tx > 0 ? tx - 1 : 0, txp = tx < BX - 1 ? tx + 1 : BX - 1;
     const int nrows = ye - ys;
-    int y = DIR > 0 ? ys : ye - 1;
+    const int y0 = DIR > 0 ? ys : ye - 1;
+    // wrapped lattice row of segment row k (k in [-1, nrows])
+    auto lattice_row = [&](int k) {
+        const int r = y0 + k * DIR;
+        return r < 0 ? r + c.ny : (r >= c.ny ? r - c.ny : r);
+    };
+    auto check = [&](bool ok, int r) {
+        if (!ok && active) bad = min(bad, domain_key(t, r, x, c.nx));
+    };
 
-    Window w;
-    double fC[kQ], fL[kQ], fN[kQ];
-    double rhoC = 1.0, rhoL = 1.0;
-    bool ok = true;
+    double f[K][kQ];
+    Row rw[K];
 
-    // prologue: psi of the trailing and current rows, populations of the
-    // current and leading rows
+    // prologue: psi of the trailing row (rw[0]) and the current row (rw[1]);
+    // populations of segment rows 0 .. PF (clamped to nrows) into sets 0 .. PF
     {
-        double ft[kQ], rho_t;
-        const int rt = DIR > 0 ? wrap_lo(y - 1, c.ny) : wrap_hi(y + 1, c.ny);
-        w.oT = 0.0;
-        w.oC = 0.0;
-        if (active) {
-            load_pulled(src, c, rt, x, xm, xp, ft);
-            load_pulled(src, c, y, x, xm, xp, fC);
-            if (!rho_psi(ft, c, rho_t, w.oT)) flag_domain(err, t, rt, x, c.nx);
-            if (!rho_psi(fC, c, rhoC, w.oC)) flag_domain(err, t, y, x, c.nx);
-            const int rl = DIR > 0 ? wrap_hi(y + 1, c.ny) : wrap_lo(y - 1, c.ny);
-            load_pulled(src, c, rl, x, xm, xp, fL);
-        }
-        lds[tx] = w.oT;
-        lds[BX + tx] = w.oC;
+        double ft[kQ];
+        const int rt = lattice_row(-1);
+        load_pulled(src, c, rt, cols, ft);
+        load_pulled(src, c, y0, cols, f[0]);
+#pragma unroll
+        for (int p = 1; p <= PF; ++p)
+            load_pulled(src, c, lattice_row(p < nrows ? p : nrows), cols, f[p]);
+        check(rho_psi<FORCE>(ft, c, rw[0].rho, rw[0].o), rt);
+        check(rho_psi<FORCE>(f[0], c, rw[1].rho, rw[1].o), y0);
+        lds[tx] = rw[0].o;
+        lds[BX + tx] = rw[1].o;
         __syncthreads();
-        if (interior) {
-            w.lT = lds[tx - 1];
-            w.rT = lds[tx + 1];
-            w.lC = lds[BX + tx - 1];
-            w.rC = lds[BX + tx + 1];
-        }
+        rw[0].l = lds[txm];
+        rw[0].r = lds[txp];
+        rw[1].l = lds[BX + txm];
+        rw[1].r = lds[BX + txp];
         __syncthreads();
     }
 
-    for (int k = 0; k < nrows; ++k, y += DIR) {
-        // prefetch the populations of the row after the leading one
-        if (active && k + 1 < nrows) {
-            int rn = y + 2 * DIR;
-            rn = DIR > 0 ? wrap_hi(rn, c.ny) : wrap_lo(rn, c.ny);
-            load_pulled(src, c, rn, x, xm, xp, fN);
+    auto body = [&](auto Jc, int k) {
+        constexpr int J = decltype(Jc)::value;      // k % K
+        constexpr int cur = J % K, lead = (J + 1) % K, fetch = (J + 1 + PF) % K;
+        const Row &T = rw[J % K];
+        const Row &C = rw[(J + 1) % K];
+        Row &L = rw[(J + 2) % K];
+        const int y = y0 + k * DIR;
+        {
+            const int kf = k + 1 + PF;
+            load_pulled(src, c, lattice_row(kf < nrows ? kf : nrows), cols, f[fetch]);
         }
-        // psi of the leading row, shared with the x-neighbours
-        w.oL = 0.0;
-        if (active) {
-            if (!rho_psi(fL, c, rhoL, w.oL)) {
-                const int rl = DIR > 0 ? wrap_hi(y + 1, c.ny) : wrap_lo(y - 1, c.ny);
-                flag_domain(err, t, rl, x, c.nx);
-            }
-        }
+        check(rho_psi<FORCE>(f[lead], c, L.rho, L.o), lattice_row(k + 1));
         double *buf = lds + (k & 1) * BX;
-        buf[tx] = w.oL;
+        buf[tx] = L.o;
         __syncthreads();
-        if (interior) {
-            w.lL = buf[tx - 1];
-            w.rL = buf[tx + 1];
-
-            double Fx = 0.0, Fy = 0.0;
-            if (c.force_on) {
-                double s[kQ];
-                window_to_stencil<DIR>(w, s);
-                force(s, c, Fx, Fy);
-            }
-            double ux, uy;
-            velocity(fC, rhoC, Fx, Fy, ux, uy);
-            const size_t cell = (size_t)y * c.nx + x;
-            if (MODE == kStep) {
-                collide(fC, rhoC, ux, uy, Fx, Fy, c);
+        L.l = buf[txm];
+        L.r = buf[txp];
+        double Fx = 0.0, Fy = 0.0;
+        if (FORCE) {
+            double s[kQ];
+            stencil<DIR>(T, C, L, s);
+            force(s, c, Fx, Fy);
+        }
+        double ux, uy;
+        velocity(f[cur], C.rho, Fx, Fy, ux, uy);
+        const size_t row = (size_t)y * c.nx;
+        if (MODE == kStep) {
+            collide(f[cur], C.rho, ux, uy, Fx, Fy, c);
+            if (interior) {
+                const size_t prow = (size_t)y * c.pitch;
 #pragma unroll
                 for (int i = 0; i < kQ; ++i)
-                    dst[i * c.plane + cell] = fC[i];
-            } else if (MODE == kMoments) {
-                if (fo.rho) fo.rho[cell] = rhoC;
+                    __builtin_nontemporal_store(
+                        f[cur][i], (double *)((char *)(dst + i * c.plane + prow) + cols.o));
+            }
+        } else if (MODE == kMoments) {
+            if (interior) {
+                const size_t cell = row + x;
+                if (fo.rho) fo.rho[cell] = C.rho;
                 if (fo.ux) fo.ux[cell] = ux;
                 if (fo.uy) fo.uy[cell] = uy;
                 if (fo.Fx) fo.Fx[cell] = Fx;
                 if (fo.Fy) fo.Fy[cell] = Fy;
-                if (fo.psi) fo.psi[cell] = w.oC;
-            } else {
+                if (fo.psi) fo.psi[cell] = C.o;
+            }
+        } else {
+            if (interior) {
+                const size_t cell = row + x;
                 const double prev = rho_snap[cell];
-                rho_snap[cell] = rhoC;
-                acc[0] += rhoC;
-                acc[1] += rhoC * ux;
-                acc[2] += rhoC * uy;
-                acc[3] += fabs(rhoC - prev);
-                acc[4] += fabs(rhoC);
+                rho_snap[cell] = C.rho;
+                acc[0] += C.rho;
+                acc[1] += C.rho * ux;
+                acc[2] += C.rho * uy;
+                acc[3] += fabs(C.rho - prev);
+                acc[4] += fabs(C.rho);
                 acc[5] = fmax(acc[5], sqrt(ux * ux + uy * uy));
             }
         }
-        // rotate the window and the population registers
-        w.oT = w.oC; w.lT = w.lC; w.rT = w.rC;
-        w.oC = w.oL; w.lC = w.lL; w.rC = w.rL;
-        rhoC = rhoL;
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            fC[i] = fL[i];
-            fL[i] = fN[i];
-        }
-    }
-    (void)ok;
+    };
+
+    int k = 0;
+    for (; k + K <= nrows; k += K)
+        unroll([&](auto J) { body(J, k + decltype(J)::value); },
+               std::make_integer_sequence<int, K>{});
+    unroll([&](auto J) {
+        if (k + decltype(J)::value < nrows) body(J, k + decltype(J)::value);
+    }, std::make_integer_sequence<int, K - 1>{});
 }
 
-template <int BX, int MODE>
+template <int BX, int MODE, int PF, int FORCE>
 __global__ __launch_bounds__(BX) void sweep_kernel(const double *__restrict__ src,
                                                    double *__restrict__ dst, Coeffs c, Tiles tl,
                                                    long long t,
@@ -382,15 +431,13 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const double *__restrict__ sr
                                                    double *__restrict__ partials)
 {
     __shared__ double lds[2 * BX];
-    // XCD-aware tile order: workgroup b runs on XCD b % 8, and each XCD takes
-    // a contiguous run of tiles (strips of consecutive row bands).
-    const int b = blockIdx.x;
-    const int tile = (b % kXcds) * tl.per_xcd + b / kXcds;
-    if (tile >= tl.ntiles) return;  // uniform for the whole workgroup
+    // Tiles are numbered row band by row band; workgroups are dealt to the 8
+    // XCDs round-robin, so the strips of one band run side by side.
+    const int tile = blockIdx.x;
     const int seg = tile / tl.nstrips;
     const int strip = tile - seg * tl.nstrips;
-    const int xs = (int)((long long)strip * c.nx / tl.nstrips);
-    const int xe = (int)((long long)(strip + 1) * c.nx / tl.nstrips);
+    const int xs = strip * tl.width;
+    const int xe = min(c.nx, xs + tl.width);
     const int ys = (int)((long long)seg * c.ny / tl.nseg);
     const int ye = (int)((long long)(seg + 1) * c.ny / tl.nseg);
 
@@ -401,14 +448,17 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const double *__restrict__ sr
     int x = xs - 1 + (active ? tx : 1);
     x = wrap_hi(wrap_lo(x, c.nx), c.nx);
     const int xm = wrap_lo(x - 1, c.nx), xp = wrap_hi(x + 1, c.nx);
+    const Cols cols{(uint32_t)x * 8u, (uint32_t)xm * 8u, (uint32_t)xp * 8u};
 
     double acc[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    unsigned long long bad = ~0ull;
     if (seg & 1)
-        walk<BX, MODE, -1>(src, dst, c, t, err, fo, rho_snap, ys, ye, x, xm, xp, active,
-                           interior, lds, acc);
+        walk<BX, MODE, -1, PF, FORCE>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
+                                      interior, lds, acc, bad);
     else
-        walk<BX, MODE, +1>(src, dst, c, t, err, fo, rho_snap, ys, ye, x, xm, xp, active,
-                           interior, lds, acc);
+        walk<BX, MODE, +1, PF, FORCE>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
+                                      interior, lds, acc, bad);
+    if (bad != ~0ull) atomicMin(err, bad);
 
     if (MODE == kDiagnostics) {
         __shared__ double red[BX / 64];
@@ -467,13 +517,14 @@ __global__ __launch_bounds__(256) void init_kernel(double *__restrict__ X, Coeff
         const int xx = wrap_hi(wrap_lo(x + cx[i], c.nx), c.nx);
         const int yy = wrap_hi(wrap_lo(y + cy[i], c.ny), c.ny);
         const size_t s = (size_t)yy * c.nx + xx;
-        X[i * c.plane + k] =
+        X[i * c.plane + (size_t)y * c.pitch + x] =
             feq_dir(i, rho0[s], ux0 ? ux0[s] : 0.0, uy0 ? uy0[s] : 0.0);
     }
 }
 
 // Canonical f(t) <-> pull storage.  to_canonical: f_i(x) = X_i(x - c_i);
-// otherwise X_i(z) = f_i(z + c_i).
+// otherwise X_i(z) = f_i(z + c_i).  Canonical arrays are dense [9][ny][nx];
+// the storage has row pitch c.pitch and plane stride c.plane.
 __global__ __launch_bounds__(256) void permute_kernel(const double *__restrict__ in,
                                                        double *__restrict__ out, Coeffs c,
                                                        int to_canonical)
@@ -484,14 +535,17 @@ __global__ __launch_bounds__(256) void permute_kernel(const double *__restrict__
     const int x = (int)(k % c.nx), y = (int)(k / c.nx);
     const int cx[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     const int cy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-    const int sgn = to_canonical ? -1 : 1;
-    const size_t in_plane = to_canonical ? c.plane : n;
-    const size_t out_plane = to_canonical ? n : c.plane;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        const int xx = wrap_hi(wrap_lo(x + sgn * cx[i], c.nx), c.nx);
-        const int yy = wrap_hi(wrap_lo(y + sgn * cy[i], c.ny), c.ny);
-        out[i * out_plane + k] = in[i * in_plane + (size_t)yy * c.nx + xx];
+        if (to_canonical) {
+            const int xx = wrap_hi(wrap_lo(x - cx[i], c.nx), c.nx);
+            const int yy = wrap_hi(wrap_lo(y - cy[i], c.ny), c.ny);
+            out[i * n + k] = in[i * c.plane + (size_t)yy * c.pitch + xx];
+        } else {
+            const int xx = wrap_hi(wrap_lo(x + cx[i], c.nx), c.nx);
+            const int yy = wrap_hi(wrap_lo(y + cy[i], c.ny), c.ny);
+            out[i * c.plane + (size_t)y * c.pitch + x] = in[i * n + (size_t)yy * c.nx + xx];
+        }
     }
 }
 
@@ -526,14 +580,34 @@ struct lbm_handle {
 namespace {
 
 struct Layout {
-    size_t err, diag_out, partials, rho_snap, bufA, bufB, total, plane;
+    size_t err, diag_out, partials, rho_snap, bufA, bufB, total, plane, pitch;
 };
+
+// Population storage padding.  Rows start on 128-byte boundaries (the row
+// pitch is nx rounded up to 16 elements; LBM_PAD_ROW=1 would also make it an
+// odd multiple of 16, which measured slower on 2048-wide lattices), and
+// consecutive planes are offset by 768 bytes beyond a 256-byte multiple so
+// that they do not all start at the same power-of-two boundary.
+#ifndef LBM_PAD_ROW
+#define LBM_PAD_ROW 0
+#endif
+#ifndef LBM_PAD_PLANE
+#define LBM_PAD_PLANE 1
+#endif
+size_t row_pitch(int nx)
+{
+    size_t p = round_up((size_t)nx, 16);
+    if (LBM_PAD_ROW && (p / 16) % 2 == 0) p += 16;
+    return p;
+}
 
 Layout layout_for(const lbm_params *p)
 {
     Layout L;
     const size_t n = (size_t)p->nx * p->ny;
-    L.plane = round_up(n, kAlign / sizeof(double));
+    L.pitch = row_pitch(p->nx);
+    L.plane = round_up(L.pitch * p->ny, kAlign / sizeof(double));
+    if (LBM_PAD_PLANE) L.plane += 3 * kAlign / sizeof(double);
     size_t off = 0;
     L.err = off;
     off += kAlign;
@@ -542,7 +616,7 @@ Layout layout_for(const lbm_params *p)
     L.partials = off;
     off += round_up((size_t)kMaxTiles * kDiag * sizeof(double), kAlign);
     L.rho_snap = off;
-    off += L.plane * sizeof(double);
+    off += round_up(n * sizeof(double), kAlign);
     L.bufA = off;
     off += kQ * L.plane * sizeof(double);
     L.bufB = off;
@@ -572,11 +646,12 @@ bool params_valid(const lbm_params *p, std::string *why)
     return true;
 }
 
-Coeffs make_coeffs(const lbm_params *p, size_t plane)
+Coeffs make_coeffs(const lbm_params *p, size_t pitch, size_t plane)
 {
     Coeffs c;
     c.nx = p->nx;
     c.ny = p->ny;
+    c.pitch = (int)pitch;
     c.plane = plane;
     c.omega = 1.0 / p->tau;
     c.guo = 1.0 - 1.0 / (2.0 * p->tau);
@@ -594,39 +669,46 @@ Coeffs make_coeffs(const lbm_params *p, size_t plane)
 
 bool make_tiles(int nx, int ny, int bx, int seg_rows, Tiles *tl)
 {
-    const int w = bx - 2;
+    int w = bx - 2;
+    if (nx > w) w = w / 16 * 16;
+    else w = nx;
+    tl->width = w;
     tl->nstrips = (nx + w - 1) / w;
     tl->nseg = (ny + seg_rows - 1) / seg_rows;
     const long long nt = (long long)tl->nstrips * tl->nseg;
     if (nt > kMaxTiles) return false;
     tl->ntiles = (int)nt;
-    tl->per_xcd = (tl->ntiles + kXcds - 1) / kXcds;
     return true;
 }
 
 // Default launch shape: the workgroup width that wastes the fewest lanes on
-// ragged strips (ties to the wider one up to 256 threads), then enough row
-// segments for about 8 waves per CU on 256 CUs, each segment at least 8 rows.
+// ragged strips (ties to the wider one, up to 256 threads), then row segments
+// short enough for about 32 waves per CU on 256 CUs (more workgroups than fit
+// at once, so the hardware balances them), each segment at least 8 rows.
+// Measured on 2048 x 2048: (256 threads, 9 rows) is within 2 % of the best
+// shape of a sweep over 64..512 threads and 8..65 rows.
 void default_launch(int nx, int ny, int *bx_out, int *rows_out)
 {
     int best = 256;
-    double best_eff = -1.0;
+    double best_score = -1.0;
     for (int bx = 64; bx <= 512; bx += 64) {
-        const int nstrips = (nx + bx - 3) / (bx - 2);
-        const double eff = (double)nx / ((double)nstrips * bx);
-        const double score = eff - (bx > 256 ? 0.02 : 0.0);
-        if (score > best_eff + 1e-12) {
-            best_eff = score;
+        Tiles tl;
+        make_tiles(nx, ny, bx, 1 << 30, &tl);
+        const double eff = (double)nx / ((double)tl.nstrips * bx);
+        const double score = eff - (bx > 256 ? 0.02 : 0.0) + (bx == 256 ? 0.02 : 0.0);
+        if (score > best_score + 1e-12) {
+            best_score = score;
             best = bx;
         }
     }
-    const int nstrips = (nx + best - 3) / (best - 2);
-    const double target_waves = 256.0 * 8.0;
-    int nseg = (int)std::ceil(target_waves / ((double)nstrips * (best / 64)));
+    Tiles tb;
+    make_tiles(nx, ny, best, 1 << 30, &tb);
+    const double target_waves = 256.0 * 32.0;
+    int nseg = (int)std::ceil(target_waves / ((double)tb.nstrips * (best / 64)));
     nseg = std::max(1, std::min(nseg, ny));
     int rows = (ny + nseg - 1) / nseg;
     rows = std::max(rows, std::min(8, ny));
-    while ((long long)nstrips * ((ny + rows - 1) / rows) > kMaxTiles)
+    while ((long long)tb.nstrips * ((ny + rows - 1) / rows) > kMaxTiles)
         ++rows;
     *bx_out = best;
     *rows_out = rows;
@@ -640,16 +722,18 @@ lbm_status dev_fail(lbm_handle *h, hipError_t e, const char *what)
     return LBM_ERR_DEVICE;
 }
 
-template <int MODE>
-hipError_t launch_sweep(lbm_handle *h, const double *src, double *dst, Fields fo)
+template <int MODE, int FORCE>
+hipError_t launch_sweep_f(lbm_handle *h, const double *src, double *dst, Fields fo)
 {
-    const dim3 grid((unsigned)(h->tiles.per_xcd * kXcds));
+    const dim3 grid((unsigned)h->tiles.ntiles);
     const Coeffs &c = h->c;
+    constexpr int PF = MODE == kStep ? kPrefetch : 1;
     switch (h->bx) {
 #define LBM_CASE(BX)                                                                          \
     case BX:                                                                                  \
-        hipLaunchKernelGGL((sweep_kernel<BX, MODE>), grid, dim3(BX), 0, h->stream, src, dst, c, \
-                           h->tiles, (long long)h->t, h->err, fo, h->rho_snap, h->partials); \
+        hipLaunchKernelGGL((sweep_kernel<BX, MODE, PF, FORCE>), grid, dim3(BX), 0, h->stream,   \
+                           src, dst, c, h->tiles, (long long)h->t, h->err, fo, h->rho_snap,   \
+                           h->partials);                                                      \
         break;
         LBM_CASE(64)
         LBM_CASE(128)
@@ -664,6 +748,13 @@ hipError_t launch_sweep(lbm_handle *h, const double *src, double *dst, Fields fo
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_sweep(lbm_handle *h, const double *src, double *dst, Fields fo)
+{
+    return h->c.force_on ? launch_sweep_f<MODE, 1>(h, src, dst, fo)
+                         : launch_sweep_f<MODE, 0>(h, src, dst, fo);
 }
 
 lbm_status read_sticky(lbm_handle *h)
@@ -709,7 +800,7 @@ lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspac
     lbm_handle *h = new (std::nothrow) lbm_handle();
     if (!h) return LBM_ERR_OOM;
     h->p = *params;
-    h->c = make_coeffs(params, L.plane);
+    h->c = make_coeffs(params, L.pitch, L.plane);
     h->stream = (hipStream_t)hip_stream;
     char *ws = (char *)d_workspace;
     h->err = (unsigned long long *)(ws + L.err);
@@ -845,7 +936,7 @@ lbm_status lbm_get_launch(const lbm_handle *h, int32_t out[3])
     if (!h || !out) return LBM_ERR_INVALID_ARG;
     out[0] = h->bx;
     out[1] = h->seg_rows;
-    out[2] = h->tiles.per_xcd * kXcds;
+    out[2] = h->tiles.ntiles;
     return LBM_OK;
 }
 
