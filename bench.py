@@ -14,7 +14,11 @@ written), using the kernel's average duration timed with HIP events on the
 library's stream.  `cpu_baseline` times the CPU oracle on a bounded sample of
 the same workload.
 
+--storage f32 / f16 runs the same workload with populations stored as FP32 /
+FP16 deviations from w_i rho_ref (FP32 arithmetic; 72 / 36 bytes per cell).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--storage f64|f32|f16]
        python bench.py --copy-calibration   (plain copy kernel for PMC scaling)
 """
 import argparse
@@ -28,13 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-BYTES_PER_CELL = 144          # 9 FP64 reads + 9 FP64 writes per cell update
+BYTES_PER_CELL = {"f64": 144, "f32": 72, "f16": 36}  # 9 reads + 9 writes per cell update
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 METRIC = "MLUPS/GPU and % HBM roofline (FP64 vs FP32/FP16-shifted); p50/p99 time-to-result"
 N = 2048
 TEMPS = (0.6, 0.7, 0.8, 0.9)
 KERNEL_SRC = os.path.join(ROOT, "paper_2003_07968_amd", "csrc", "lbm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_f64_2048.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_{storage}_2048.json")
 
 
 def err(msg):
@@ -46,12 +50,13 @@ def source_digest():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(storage):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
     were taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILE.format(storage=storage)
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel_source_sha256_16") != source_digest():
         return None
@@ -98,6 +103,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--storage", choices=sorted(BYTES_PER_CELL), default="f64")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -118,6 +124,8 @@ def main():
     lats = []
     for tr in TEMPS:
         p, rho0 = W.slab_case(n=N, tr=tr)
+        p["storage"] = W.STORAGE[args.storage]
+        p["rho_ref"] = W.shift_reference(rho0, args.storage)
         lats.append(lbm.Lattice(p, rho0))
     launch = lats[0].launch()
     err(f"lattices ready, launch shape {launch}")
@@ -151,8 +159,9 @@ def main():
     seconds = gpu_ms / 1e3
     mlups = cells * args.steps / seconds / 1e6
     launch_ms = gpu_ms / (args.steps * len(lats))
-    achieved = BYTES_PER_CELL * N * N / (launch_ms / 1e3) / 1e9
-    traffic = measured_traffic()
+    bpc = BYTES_PER_CELL[args.storage]
+    achieved = bpc * N * N / (launch_ms / 1e3) / 1e9
+    traffic = measured_traffic(args.storage)
 
     out = {
         "metric": METRIC,
@@ -165,14 +174,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
+                  "f16": "f32 arithmetic, f16-shifted storage"}[args.storage],
         "data": "synthetic",
         "config": {
-            "workload": "D2Q9 2048x2048 periodic flat slab, FP64, T_r in {0.6,0.7,0.8,0.9} "
+            "workload": "D2Q9 2048x2048 periodic flat slab, T_r in {0.6,0.7,0.8,0.9} "
                         "(four lattices), tau=1, Carnahan-Starling a=1 b=4 R=1, G=-1, "
                         "eps=1.73, sigma=1, W=2, seeded +-1e-3 noise",
+            "storage": args.storage,
             "lattices": len(lats), "nx": N, "ny": N,
-            "bytes_per_cell_update": BYTES_PER_CELL,
+            "bytes_per_cell_update": bpc,
             "launch_block_x_seg_rows_workgroups": list(launch),
         },
         "roofline": {
@@ -182,11 +193,11 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "sweep_kernel (step mode)",
+            "kernel": f"sweep_kernel (step mode, {args.storage} storage)",
             "kernel_avg_ms": round(launch_ms, 5),
         },
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.storage == "f64":
         err("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -22,7 +22,8 @@
  *             + (c_ia c_ib - cs^2 d_ab) F_a u_b / cs^4],  f^eq of Eq. SEDF
  *
  * with the D2Q9 velocities and weights of Sec. II.A (Eq. VelocitySet),
- * cs^2 = 1/3, in FP64.
+ * cs^2 = 1/3, in FP64 (or, with reduced-precision storage, FP32; see
+ * lbm_storage).
  *
  * Conventions.
  *   - Every function is extern "C", returns an lbm_status (0 = LBM_OK) or a
@@ -66,7 +67,11 @@ typedef enum {
 } lbm_status;
 
 typedef enum {
-    LBM_STORE_F64 = 0 /* populations stored in FP64 */
+    LBM_STORE_F64 = 0,         /* populations stored in FP64, FP64 arithmetic           */
+    LBM_STORE_F32_SHIFTED = 1, /* stored as FP32 deviations f_i - w_i rho_ref, FP32
+                                  arithmetic (72 bytes per cell update)                */
+    LBM_STORE_F16_SHIFTED = 2  /* stored as FP16 (IEEE binary16) deviations, FP32
+                                  arithmetic (36 bytes per cell update)                */
 } lbm_storage;
 
 /* Physical and numerical parameters, named as in the paper. */
@@ -82,16 +87,22 @@ typedef struct {
     int32_t force_on; /* 0: F = 0, plain BGK; 1: the force of Eq. IFT              */
     int32_t m2_trace_alt; /* 0: M2_bb as the trace of Eq. SOMED; 1: the
                              alternative 2 cs^2 (M0 - psi) stated after Eq. DFTCST */
-    int32_t storage;  /* lbm_storage; only LBM_STORE_F64                           */
-    double rho_ref;   /* reference density for shifted storage; unused for F64     */
+    int32_t storage;  /* lbm_storage.  In the shifted modes each population is kept
+                         as d_i = f_i - w_i rho_ref rounded to the storage type
+                         (round to nearest even) after every step; density,
+                         force, velocity and collision are evaluated in FP32 from
+                         them.  Diagnostics sums stay FP64.                      */
+    double rho_ref;   /* reference density of the shifted modes (normally the mean
+                         initial density); ignored for LBM_STORE_F64              */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
 
 /* Bytes of device workspace lbm_init needs for these parameters (0 if they are
  * invalid).  The workspace holds two population copies (2 * 9 * nx * ny
- * doubles), a density snapshot for the steady-state criterion and a few KB of
- * reduction scratch and error word. */
+ * elements of the storage type, rows padded to 128 bytes), a density snapshot
+ * for the steady-state criterion (FP64), 1.5 MB of reduction scratch and the
+ * error word. */
 size_t lbm_workspace_bytes(const lbm_params *params);
 
 /* Validate params, carve the workspace (device memory of at least
@@ -130,12 +141,14 @@ lbm_status lbm_moments(lbm_handle *h, double *d_rho, double *d_ux, double *d_uy,
  * order (deterministic for a given lattice size).  Synchronous. */
 lbm_status lbm_diagnostics(lbm_handle *h, double out[6]);
 
-/* Copy f(t) out to d_f ([9][ny][nx] FP64, device).  Synchronous. */
+/* Copy f(t) out to d_f ([9][ny][nx] FP64, device).  Synchronous.  With shifted
+ * storage the values are w_i rho_ref + d_i, exactly. */
 lbm_status lbm_get_populations(lbm_handle *h, double *d_f);
 
 /* Replace the state by f(t) = d_f ([9][ny][nx] FP64, device) and set the
- * time counter to t >= 0 (checkpoint restart).  Synchronous.  Clears nothing
- * else: a sticky error stays. */
+ * time counter to t >= 0 (checkpoint restart).  With shifted storage each
+ * f_i - w_i rho_ref is rounded to the storage type.  Synchronous.  Clears
+ * nothing else: a sticky error stays. */
 lbm_status lbm_set_populations(lbm_handle *h, const double *d_f, int64_t t);
 
 /* Number of completed steps. */

@@ -39,6 +39,44 @@ int lbmref_threads(void)
 #endif
 }
 
+/* Rounding to the storage formats.  binary16 has 11 significant bits, normal
+ * numbers from 2^-14 to 65504 and subnormals spaced 2^-24; values from 65520
+ * up round to infinity.  The spacing of representable values around |x| is
+ * 2^(e - 11) for |x| in [2^(e-1), 2^e), never below 2^-24, so rounding is a
+ * scaling by a power of two, an integer round (ties to even) and the scaling
+ * back, all exact except the round itself. */
+static double round_binary16(double x)
+{
+    if (!isfinite(x) || x == 0.0) return x;
+    double a = fabs(x);
+    if (a >= 65520.0) return copysign(INFINITY, x);
+    int e;
+    frexp(a, &e);
+    int ulp_exp = e - 11;
+    if (ulp_exp < -24) ulp_exp = -24;
+    double r = nearbyint(ldexp(a, -ulp_exp));
+    return copysign(ldexp(r, ulp_exp), x);
+}
+
+double lbmref_quantize(int32_t storage, double x)
+{
+    if (storage == 1) return (double)(float)x;
+    if (storage == 2) return round_binary16(x);
+    return x;
+}
+
+/* Reduced-precision storage: f_i = w_i rho_ref + round(f_i - w_i rho_ref). */
+static void store_round(const lbmref_params *p, double *f, size_t n)
+{
+    if (!p->storage) return;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < 9; ++i)
+        for (size_t k = 0; k < n; ++k) {
+            double base = W[i] * p->rho_ref;
+            f[(size_t)i * n + k] = base + lbmref_quantize(p->storage, f[(size_t)i * n + k] - base);
+        }
+}
+
 /* Carnahan-Starling equation of state, Sec. IV.A (Eq. CSEOS):
  * P = k [ c rho T (1 + b rho + (b rho)^2 - (b rho)^3) / (1 - b rho)^3 - a rho^2 ]. */
 double lbmref_eos_pressure(const lbmref_params *p, double rho)
@@ -213,6 +251,7 @@ static int check_params(const lbmref_params *p)
     if (!p || p->nx < 3 || p->ny < 3) return LBMREF_ERR_INVALID_ARG;
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return LBMREF_ERR_INVALID_ARG;
     if (!(p->G != 0.0) || !isfinite(p->G)) return LBMREF_ERR_INVALID_ARG;
+    if (p->storage < 0 || p->storage > 2 || !isfinite(p->rho_ref)) return LBMREF_ERR_INVALID_ARG;
     return LBMREF_OK;
 }
 
@@ -229,6 +268,7 @@ int lbmref_init(const lbmref_params *p, const double *rho0, const double *ux0,
         for (int i = 0; i < 9; ++i)
             f[(size_t)i * n + k] = feq[i];
     }
+    store_round(p, f, n);
     return LBMREF_OK;
 }
 
@@ -361,6 +401,8 @@ int lbmref_step(const lbmref_params *p, double *f, int64_t nsteps, lbmref_fault 
                     fpost[(size_t)i * n + k] = fi - (fi - feq[i]) / p->tau + S[i];
                 }
             }
+        /* phase: storage rounding (reduced-precision storage only) */
+        store_round(p, fpost, n);
         /* phase: streaming, periodic */
 #pragma omp parallel for schedule(static)
         for (int y = 0; y < p->ny; ++y)

@@ -43,6 +43,11 @@ typedef struct {
     double eos_a, eos_b, eos_c, eos_k, T; /* Carnahan-Starling, Eq. CSEOS     */
     int32_t force_on;     /* 0: F = 0 (plain BGK); 1: the force of Eq. IFT    */
     int32_t m2_trace_alt; /* 0: direct trace of Eq. SOMED; 1: 2 cs^2 (M0-psi) */
+    int32_t storage;      /* 0: exact FP64 state; 1, 2: the state is kept as
+                             deviations f_i - w_i rho_ref rounded to IEEE
+                             binary32 (1) or binary16 (2) after every step and
+                             at initialisation (reduced-precision storage)    */
+    double rho_ref;       /* reference density of the stored deviations       */
 } lbmref_params;
 
 /* Diagnostic record of the first domain failure (cell = y*nx + x). */
@@ -77,6 +82,11 @@ int lbmref_moments(const lbmref_params *p, const double *f, double *rho,
 int lbmref_step(const lbmref_params *p, double *f, int64_t nsteps,
                 lbmref_fault *fault);                     /* Eq. TLBE, nsteps times    */
 int lbmref_threads(void);                                  /* OpenMP threads it will use */
+
+/* Round x to the nearest value of the storage format (ties to even):
+ * 0 -> x unchanged, 1 -> IEEE binary32, 2 -> IEEE binary16 (with subnormals,
+ * overflow to infinity). */
+double lbmref_quantize(int32_t storage, double x);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,7 @@ class Params(ctypes.Structure):
         ("eos_a", ctypes.c_double), ("eos_b", ctypes.c_double),
         ("eos_c", ctypes.c_double), ("eos_k", ctypes.c_double), ("T", ctypes.c_double),
         ("force_on", ctypes.c_int32), ("m2_trace_alt", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("rho_ref", ctypes.c_double),
     ]
 
 
@@ -71,6 +72,8 @@ def _load():
         lib.lbmref_moments.argtypes = [P, _DP] + [_DP] * 6 + [ctypes.POINTER(Fault)]
         lib.lbmref_step.argtypes = [P, _DP, ctypes.c_int64, ctypes.POINTER(Fault)]
         lib.lbmref_threads.argtypes = []
+        lib.lbmref_quantize.argtypes = [ctypes.c_int32, ctypes.c_double]
+        lib.lbmref_quantize.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -82,12 +85,20 @@ def _ptr(a):
     return a.ctypes.data_as(_DP)
 
 
+STORE_F64, STORE_F32, STORE_F16 = 0, 1, 2
+
+
 def make_params(nx, ny, tau=1.0, G=-1.0, epsilon=1.73, sigma=1.0, eos=(1.0, 1.0, 1.0, 1.0),
-                T=0.0, force_on=True, m2_trace_alt=False) -> Params:
+                T=0.0, force_on=True, m2_trace_alt=False, storage=0, rho_ref=0.0) -> Params:
     a, b, c, k = eos
     return Params(int(nx), int(ny), float(tau), float(G), float(epsilon), float(sigma),
                   float(a), float(b), float(c), float(k), float(T), int(bool(force_on)),
-                  int(bool(m2_trace_alt)))
+                  int(bool(m2_trace_alt)), int(storage), float(rho_ref))
+
+
+def quantize(storage, x):
+    """Round x to the storage format (1: binary32, 2: binary16; 0: unchanged)."""
+    return _load().lbmref_quantize(int(storage), float(x))
 
 
 def threads() -> int:

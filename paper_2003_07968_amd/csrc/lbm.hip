@@ -5,7 +5,12 @@
 // streaming (Eq. TLBE), density (Eq. FD), Carnahan-Starling pressure
 // (Eq. CSEOS), pseudopotential (Eq. DED), psi moments (Eqs. FOMED, SOMED), the
 // proposed force (Eq. IFT), velocity (Eq. FMD) and the Guo-forced BGK
-// collision (Eqs. BGKCO, SEDF, GFS, GFSBGK).  Everything is FP64.
+// collision (Eqs. BGKCO, SEDF, GFS, GFSBGK).
+//
+// Storage modes: FP64 populations with FP64 arithmetic, or populations kept
+// as deviations d_i = f_i - w_i rho_ref in FP32 or FP16 with FP32 arithmetic
+// (rho_ref is a reference density, normally the mean).  The diagnostics
+// reductions are FP64 in every mode.
 //
 // Kernel design (one fused pass per step, HBM-bound):
 //   * populations are structure-of-arrays planes X_i[y][x] holding the
@@ -49,6 +54,26 @@ constexpr int kDiag = 6;          // diagnostics values per workgroup
 constexpr int kPrefetch = LBM_PREFETCH; // rows in flight beyond the leading row (step sweep)
 constexpr size_t kAlign = 256;
 
+// Storage formats of the populations and the arithmetic type used with them.
+template <int ST> struct Store;
+template <> struct Store<LBM_STORE_F64> {
+    using E = double;  // stored element
+    using R = double;  // arithmetic
+};
+template <> struct Store<LBM_STORE_F32_SHIFTED> {
+    using E = float;
+    using R = float;
+};
+template <> struct Store<LBM_STORE_F16_SHIFTED> {
+    using E = _Float16;
+    using R = float;
+};
+
+size_t elem_size(int storage)
+{
+    return storage == LBM_STORE_F64 ? 8 : (storage == LBM_STORE_F32_SHIFTED ? 4 : 2);
+}
+
 // Coefficients of one lattice, precomputed on the host.
 struct Coeffs {
     int nx, ny;
@@ -65,14 +90,29 @@ struct Coeffs {
     // cSC = -2G/cs^2 = -6G; cA = (3/2 eps - (sigma - 1)) cs^2 G / cs^6
     // = 9G (1.5 eps - sigma + 1); cB = (sigma - 1) cs^2 G / cs^6 = 9G (sigma - 1).
     double cSC, cA, cB;
+    double rho_ref; // populations are stored as f_i - w_i rho_ref (0 for FP64)
     int force_on;
     int trace_alt;
+    int storage;
+};
+
+// The coefficients in the arithmetic type of a storage mode.
+template <class R>
+struct Phys {
+    R omega, guo, eos_b, kcT, ka, invG, cSC, cA, cB, rho_ref;
+    int trace_alt;
+    __device__ explicit Phys(const Coeffs &c)
+        : omega((R)c.omega), guo((R)c.guo), eos_b((R)c.eos_b), kcT((R)c.kcT), ka((R)c.ka),
+          invG((R)c.invG), cSC((R)c.cSC), cA((R)c.cA), cB((R)c.cB), rho_ref((R)c.rho_ref),
+          trace_alt(c.trace_alt)
+    {
+    }
 };
 
 // Tile decomposition of one sweep.  Strip s covers interior columns
-// [s * width, min(nx, (s + 1) * width)); width is a multiple of 16 columns
-// (128 bytes) whenever the lattice needs more than one strip, so that the
-// stores of neighbouring workgroups never share a cache line.
+// [s * width, min(nx, (s + 1) * width)); width is a multiple of the storage's
+// store alignment (64-128 bytes) whenever the lattice needs more than one
+// strip, so the stores of neighbouring workgroups never share a cache line.
 struct Tiles {
     int nstrips, nseg, ntiles, width;
 };
@@ -95,49 +135,52 @@ struct Cols {
     uint32_t o, m, p;  // byte offsets of columns x, x - 1 (wrapped), x + 1 (wrapped)
 };
 
-__device__ __forceinline__ double ld(const double *__restrict__ row, uint32_t byte_off)
+template <class E, class R>
+__device__ __forceinline__ R ld(const E *__restrict__ row, uint32_t byte_off)
 {
-    return *(const double *)((const char *)row + byte_off);
+    return (R) * (const E *)((const char *)row + byte_off);
 }
 
-__device__ __forceinline__ void load_pulled(const double *__restrict__ src, const Coeffs &c,
-                                            int r, const Cols &x, double f[kQ])
+template <class E, class R>
+__device__ __forceinline__ void load_pulled(const E *__restrict__ src, const Coeffs &c, int r,
+                                            const Cols &x, R d[kQ])
 {
     const int rm = wrap_lo(r - 1, c.ny), rp = wrap_hi(r + 1, c.ny);
     const size_t P = c.plane;
-    const double *row_r = src + (size_t)r * c.pitch;
-    const double *row_m = src + (size_t)rm * c.pitch;
-    const double *row_p = src + (size_t)rp * c.pitch;
-    f[0] = ld(row_r, x.o);
-    f[1] = ld(row_r + 1 * P, x.m);
-    f[2] = ld(row_m + 2 * P, x.o);
-    f[3] = ld(row_r + 3 * P, x.p);
-    f[4] = ld(row_p + 4 * P, x.o);
-    f[5] = ld(row_m + 5 * P, x.m);
-    f[6] = ld(row_m + 6 * P, x.p);
-    f[7] = ld(row_p + 7 * P, x.p);
-    f[8] = ld(row_p + 8 * P, x.m);
+    const E *row_r = src + (size_t)r * c.pitch;
+    const E *row_m = src + (size_t)rm * c.pitch;
+    const E *row_p = src + (size_t)rp * c.pitch;
+    d[0] = ld<E, R>(row_r, x.o);
+    d[1] = ld<E, R>(row_r + 1 * P, x.m);
+    d[2] = ld<E, R>(row_m + 2 * P, x.o);
+    d[3] = ld<E, R>(row_r + 3 * P, x.p);
+    d[4] = ld<E, R>(row_p + 4 * P, x.o);
+    d[5] = ld<E, R>(row_m + 5 * P, x.m);
+    d[6] = ld<E, R>(row_m + 6 * P, x.p);
+    d[7] = ld<E, R>(row_p + 7 * P, x.p);
+    d[8] = ld<E, R>(row_p + 8 * P, x.m);
 }
 
-// Density (Eq. FD) and pseudopotential (Eqs. CSEOS, DED).  Returns false when
-// the density is outside the EOS domain (with FORCE = 0, when it is not
-// positive and finite).
-template <int FORCE>
-__device__ __forceinline__ bool rho_psi(const double f[kQ], const Coeffs &c, double &rho,
-                                        double &psi)
+// Density (Eq. FD) and pseudopotential (Eqs. CSEOS, DED) from the stored
+// deviations d_i = f_i - w_i rho_ref: rho = rho_ref + sum_i d_i.  Returns
+// false when the density is outside the EOS domain (with FORCE = 0, when it
+// is not positive and finite).
+template <int FORCE, class R>
+__device__ __forceinline__ bool rho_psi(const R d[kQ], const Phys<R> &P, R &rho, R &psi)
 {
-    rho = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
+    rho = ((((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8]) +
+          P.rho_ref;
     if (!FORCE) {
-        psi = 0.0;
-        return rho > 0.0 && rho < INFINITY;
+        psi = R(0);
+        return rho > R(0) && rho < R(INFINITY);
     }
-    const double br = c.eos_b * rho;
-    const double num = fma(br, fma(br, 1.0 - br, 1.0), 1.0);  // 1 + br + br^2 - br^3
-    const double om = 1.0 - br;
-    const double P = fma(c.kcT * rho, num / (om * om * om), -c.ka * rho * rho);
-    const double rad = fma(rho, -1.0 / 3.0, P) * c.invG;
+    const R br = P.eos_b * rho;
+    const R num = fma(br, fma(br, R(1) - br, R(1)), R(1));  // 1 + br + br^2 - br^3
+    const R om = R(1) - br;
+    const R pr = fma(P.kcT * rho, num / (om * om * om), -P.ka * rho * rho);
+    const R rad = fma(rho, R(-1.0 / 3.0), pr) * P.invG;
     psi = sqrt(rad);
-    return rho > 0.0 && br < 1.0 && rad >= 0.0 && rad < INFINITY;
+    return rho > R(0) && br < R(1) && rad >= R(0) && rad < R(INFINITY);
 }
 
 // Error key of a cell: steps first, then the cell index, so that the
@@ -147,82 +190,90 @@ __device__ __forceinline__ unsigned long long domain_key(long long t, int r, int
     return ((unsigned long long)t << 32) | (unsigned long long)((size_t)r * nx + x);
 }
 
-// Force of Eq. IFT from psi_i = psi(x + c_i) (Eqs. FOMED, SOMED, SCF,
+// Force of Eq. IFT from s_i = psi(x + c_i) (Eqs. FOMED, SOMED, SCF,
 // DFTCCC, DFTCST).
-__device__ __forceinline__ void force(const double s[kQ], const Coeffs &c, double &Fx,
-                                      double &Fy)
+template <class R>
+__device__ __forceinline__ void force(const R s[kQ], const Phys<R> &P, R &Fx, R &Fy)
 {
-    const double d13 = s[1] - s[3], d24 = s[2] - s[4];
-    const double s13 = s[1] + s[3], s24 = s[2] + s[4];
-    const double a58 = s[5] - s[7], b68 = s[6] - s[8];
-    const double s58 = (s[5] + s[6]) + (s[7] + s[8]);
-    const double M1x = d13 * (1.0 / 9.0) + (a58 - b68) * (1.0 / 36.0);
-    const double M1y = d24 * (1.0 / 9.0) + (a58 + b68) * (1.0 / 36.0);
-    const double M2xx = s[0] * (-4.0 / 27.0) + s13 * (2.0 / 27.0) - s24 * (1.0 / 27.0) +
-                        s58 * (1.0 / 54.0);
-    const double M2yy = s[0] * (-4.0 / 27.0) - s13 * (1.0 / 27.0) + s24 * (2.0 / 27.0) +
-                        s58 * (1.0 / 54.0);
-    const double M2xy = ((s[5] + s[7]) - (s[6] + s[8])) * (1.0 / 36.0);
-    const double M0 = s[0] * (4.0 / 9.0) + (s13 + s24) * (1.0 / 9.0) + s58 * (1.0 / 36.0);
-    const double tr = c.trace_alt ? (2.0 / 3.0) * (M0 - s[0]) : M2xx + M2yy;
-    const double ax = fma(M1x, M2xx, M1y * M2xy);  // (M1 . M2)_x
-    const double ay = fma(M1x, M2xy, M1y * M2yy);  // (M1 . M2)_y
-    const double sc = c.cSC * s[0], tb = c.cB * tr;
-    Fx = fma(sc, M1x, fma(c.cA, ax, tb * M1x));
-    Fy = fma(sc, M1y, fma(c.cA, ay, tb * M1y));
+    const R d13 = s[1] - s[3], d24 = s[2] - s[4];
+    const R s13 = s[1] + s[3], s24 = s[2] + s[4];
+    const R a58 = s[5] - s[7], b68 = s[6] - s[8];
+    const R s58 = (s[5] + s[6]) + (s[7] + s[8]);
+    const R M1x = d13 * R(1.0 / 9.0) + (a58 - b68) * R(1.0 / 36.0);
+    const R M1y = d24 * R(1.0 / 9.0) + (a58 + b68) * R(1.0 / 36.0);
+    const R M2xx = s[0] * R(-4.0 / 27.0) + s13 * R(2.0 / 27.0) - s24 * R(1.0 / 27.0) +
+                   s58 * R(1.0 / 54.0);
+    const R M2yy = s[0] * R(-4.0 / 27.0) - s13 * R(1.0 / 27.0) + s24 * R(2.0 / 27.0) +
+                   s58 * R(1.0 / 54.0);
+    const R M2xy = ((s[5] + s[7]) - (s[6] + s[8])) * R(1.0 / 36.0);
+    const R M0 = s[0] * R(4.0 / 9.0) + (s13 + s24) * R(1.0 / 9.0) + s58 * R(1.0 / 36.0);
+    const R tr = P.trace_alt ? R(2.0 / 3.0) * (M0 - s[0]) : M2xx + M2yy;
+    const R ax = fma(M1x, M2xx, M1y * M2xy);  // (M1 . M2)_x
+    const R ay = fma(M1x, M2xy, M1y * M2yy);  // (M1 . M2)_y
+    const R sc = P.cSC * s[0], tb = P.cB * tr;
+    Fx = fma(sc, M1x, fma(P.cA, ax, tb * M1x));
+    Fy = fma(sc, M1y, fma(P.cA, ay, tb * M1y));
 }
 
-// Velocity (Eq. FMD).
-__device__ __forceinline__ void velocity(const double f[kQ], double rho, double Fx, double Fy,
-                                         double &ux, double &uy)
+// Velocity (Eq. FMD).  The w_i rho_ref parts of the populations carry no
+// momentum, so the deviations give sum_i f_i c_i directly.
+template <class R>
+__device__ __forceinline__ void velocity(const R d[kQ], R rho, R Fx, R Fy, R &ux, R &uy)
 {
-    const double jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
-    const double jy = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
-    const double inv = 1.0 / rho;
-    ux = (jx + 0.5 * Fx) * inv;
-    uy = (jy + 0.5 * Fy) * inv;
+    const R jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]);
+    const R jy = ((d[2] - d[4]) + (d[5] + d[6])) - (d[7] + d[8]);
+    const R inv = R(1) / rho;
+    ux = (jx + R(0.5) * Fx) * inv;
+    uy = (jy + R(0.5) * Fy) * inv;
 }
 
-// BGK collision with the Guo source (Eqs. BGKCO, SEDF, GFS, GFSBGK), in place:
-//   f^eq_i = w_i rho (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
-//   S_i    = (1 - 1/(2 tau)) w_i (3 c.F + 9 (c.F)(c.u) - 3 u.F)
-//   f_i   <- f_i + (f^eq_i - f_i)/tau + S_i
+// BGK collision with the Guo source (Eqs. BGKCO, SEDF, GFS, GFSBGK), on the
+// deviations d_i = f_i - w_i rho_ref, in place:
+//   f^eq_i - w_i rho_ref = w_i ((rho - rho_ref) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
+//   S_i                  = (1 - 1/(2 tau)) w_i (3 c.F + 9 (c.F)(c.u) - 3 u.F)
+//   d_i                 <- d_i + (f^eq_i - w_i rho_ref - d_i)/tau + S_i
 // Multiply-adds are written as explicit fma(); the file is compiled without
 // implicit contraction, so every inlined copy rounds the same way.
-__device__ __forceinline__ void collide(double f[kQ], double rho, double ux, double uy,
-                                        double Fx, double Fy, const Coeffs &c)
+template <class R>
+__device__ __forceinline__ void collide(R d[kQ], R rho, R ux, R uy, R Fx, R Fy,
+                                        const Phys<R> &P)
 {
-    const double usq = fma(ux, ux, uy * uy);
-    const double uF = fma(ux, Fx, uy * Fy);
-    const double base = fma(-1.5, usq, 1.0);  // f^eq bracket without the c.u terms
-    const double sbase = -3.0 * uF;           // S bracket without the c.F terms
-    const double om = c.omega, g = c.guo;
-    const double wr0 = (4.0 / 9.0) * rho, wr1 = (1.0 / 9.0) * rho, wr2 = (1.0 / 36.0) * rho;
-    const double gw0 = g * (4.0 / 9.0), gw1 = g * (1.0 / 9.0), gw2 = g * (1.0 / 36.0);
+    const R usq = fma(ux, ux, uy * uy);
+    const R uF = fma(ux, Fx, uy * Fy);
+    const R drho = rho - P.rho_ref;
+    const R q0 = R(-1.5) * usq;   // f^eq bracket without the c.u terms
+    const R sbase = R(-3) * uF;   // S bracket without the c.F terms
+    const R om = P.omega, g = P.guo;
+    const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
+    const R gw0 = g * w0, gw1 = g * w1, gw2 = g * w2;
     {
-        const double feq = wr0 * base;
-        const double S = gw0 * sbase;
-        f[0] = fma(om, feq - f[0], f[0]) + S;
+        const R feq = w0 * fma(rho, q0, drho);
+        const R S = gw0 * sbase;
+        d[0] = fma(om, feq - d[0], d[0]) + S;
     }
-    const double cu[8] = {ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
-    const double cF[8] = {Fx, Fy, -Fx, -Fy, Fx + Fy, Fy - Fx, -Fx - Fy, Fx - Fy};
+    const R cu[8] = {ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
+    const R cF[8] = {Fx, Fy, -Fx, -Fy, Fx + Fy, Fy - Fx, -Fx - Fy, Fx - Fy};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const double wr = k < 4 ? wr1 : wr2, gw = k < 4 ? gw1 : gw2;
-        const double feq = wr * fma(cu[k], fma(4.5, cu[k], 3.0), base);
-        const double S = gw * fma(cF[k], fma(9.0, cu[k], 3.0), sbase);
-        f[k + 1] = fma(om, feq - f[k + 1], f[k + 1]) + S;
+        const R w = k < 4 ? w1 : w2, gw = k < 4 ? gw1 : gw2;
+        const R feq = w * fma(rho, fma(cu[k], fma(R(4.5), cu[k], R(3)), q0), drho);
+        const R S = gw * fma(cF[k], fma(R(9), cu[k], R(3)), sbase);
+        d[k + 1] = fma(om, feq - d[k + 1], d[k + 1]) + S;
     }
 }
 
-// Equilibrium (Eq. SEDF) of direction i.
+__device__ __forceinline__ double weight(int i)
+{
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+// Equilibrium (Eq. SEDF) of direction i, FP64.
 __device__ __forceinline__ double feq_dir(int i, double rho, double ux, double uy)
 {
     const int cx[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     const int cy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-    const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
     const double cu = cx[i] * ux + cy[i] * uy;
-    return w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
+    return weight(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
 }
 
 template <int BX>
@@ -262,18 +313,20 @@ __device__ __forceinline__ double warp_or_block_max(double v, double *lds_red)
 }
 
 // psi (own column o, x - 1 in l, x + 1 in r) and rho (own column) of one row.
+template <class R>
 struct Row {
-    double l, o, r, rho;
+    R l, o, r, rho;
 };
 
 // psi(x + c_i) for the current row C when the walk goes in direction DIR
 // (+1: the leading row L is y + 1 and the trailing row T is y - 1; -1: the
 // other way round).
-template <int DIR>
-__device__ __forceinline__ void stencil(const Row &T, const Row &C, const Row &L, double s[kQ])
+template <int DIR, class R>
+__device__ __forceinline__ void stencil(const Row<R> &T, const Row<R> &C, const Row<R> &L,
+                                        R s[kQ])
 {
-    const Row &U = DIR > 0 ? L : T;  // row y + 1
-    const Row &D = DIR > 0 ? T : L;  // row y - 1
+    const Row<R> &U = DIR > 0 ? L : T;  // row y + 1
+    const Row<R> &D = DIR > 0 ? T : L;  // row y - 1
     s[0] = C.o;
     s[1] = C.r;
     s[2] = U.o;
@@ -307,14 +360,18 @@ __device__ __forceinline__ void unroll(F &&f, std::integer_sequence<int, J...>)
 // around the loads the compiler's wait counters stay exact, so a prefetch
 // really stays in flight while the current row is computed.  Domain
 // failures are folded into a per-lane minimum key and published once.
-template <int BX, int MODE, int DIR, int PF, int FORCE>
-__device__ __forceinline__ void walk(const double *__restrict__ src, double *__restrict__ dst,
-                                     const Coeffs &c, long long t, const Fields &fo,
-                                     double *__restrict__ rho_snap, int ys, int ye, int x,
-                                     const Cols &cols, bool active, bool interior, double *lds,
+template <int BX, int MODE, int DIR, int PF, int FORCE, int ST>
+__device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ src,
+                                     typename Store<ST>::E *__restrict__ dst, const Coeffs &c,
+                                     long long t, const Fields &fo, double *__restrict__ rho_snap,
+                                     int ys, int ye, int x, const Cols &cols, bool active,
+                                     bool interior, typename Store<ST>::R *lds,
                                      double acc[kDiag], unsigned long long &bad)
 {
+    using E = typename Store<ST>::E;
+    using R = typename Store<ST>::R;
     constexpr int K = PF + 2;
+    const Phys<R> P(c);
     const int tx = threadIdx.x;
     const int txm = tx > 0 ? tx - 1 : 0, txp = tx < BX - 1 ? tx + 1 : BX - 1;
     const int nrows = ye - ys;
@@ -328,21 +385,21 @@ __device__ __forceinline__ void walk(const double *__restrict__ src, double *__r
         if (!ok && active) bad = min(bad, domain_key(t, r, x, c.nx));
     };
 
-    double f[K][kQ];
-    Row rw[K];
+    R f[K][kQ];
+    Row<R> rw[K];
 
     // prologue: psi of the trailing row (rw[0]) and the current row (rw[1]);
     // populations of segment rows 0 .. PF (clamped to nrows) into sets 0 .. PF
     {
-        double ft[kQ];
+        R ft[kQ];
         const int rt = lattice_row(-1);
-        load_pulled(src, c, rt, cols, ft);
-        load_pulled(src, c, y0, cols, f[0]);
+        load_pulled<E, R>(src, c, rt, cols, ft);
+        load_pulled<E, R>(src, c, y0, cols, f[0]);
 #pragma unroll
         for (int p = 1; p <= PF; ++p)
-            load_pulled(src, c, lattice_row(p < nrows ? p : nrows), cols, f[p]);
-        check(rho_psi<FORCE>(ft, c, rw[0].rho, rw[0].o), rt);
-        check(rho_psi<FORCE>(f[0], c, rw[1].rho, rw[1].o), y0);
+            load_pulled<E, R>(src, c, lattice_row(p < nrows ? p : nrows), cols, f[p]);
+        check(rho_psi<FORCE, R>(ft, P, rw[0].rho, rw[0].o), rt);
+        check(rho_psi<FORCE, R>(f[0], P, rw[1].rho, rw[1].o), y0);
         lds[tx] = rw[0].o;
         lds[BX + tx] = rw[1].o;
         __syncthreads();
@@ -356,59 +413,60 @@ __device__ __forceinline__ void walk(const double *__restrict__ src, double *__r
     auto body = [&](auto Jc, int k) {
         constexpr int J = decltype(Jc)::value;      // k % K
         constexpr int cur = J % K, lead = (J + 1) % K, fetch = (J + 1 + PF) % K;
-        const Row &T = rw[J % K];
-        const Row &C = rw[(J + 1) % K];
-        Row &L = rw[(J + 2) % K];
+        const Row<R> &T = rw[J % K];
+        const Row<R> &C = rw[(J + 1) % K];
+        Row<R> &L = rw[(J + 2) % K];
         const int y = y0 + k * DIR;
         {
             const int kf = k + 1 + PF;
-            load_pulled(src, c, lattice_row(kf < nrows ? kf : nrows), cols, f[fetch]);
+            load_pulled<E, R>(src, c, lattice_row(kf < nrows ? kf : nrows), cols, f[fetch]);
         }
-        check(rho_psi<FORCE>(f[lead], c, L.rho, L.o), lattice_row(k + 1));
-        double *buf = lds + (k & 1) * BX;
+        check(rho_psi<FORCE, R>(f[lead], P, L.rho, L.o), lattice_row(k + 1));
+        R *buf = lds + (k & 1) * BX;
         buf[tx] = L.o;
         __syncthreads();
         L.l = buf[txm];
         L.r = buf[txp];
-        double Fx = 0.0, Fy = 0.0;
+        R Fx = R(0), Fy = R(0);
         if (FORCE) {
-            double s[kQ];
-            stencil<DIR>(T, C, L, s);
-            force(s, c, Fx, Fy);
+            R s[kQ];
+            stencil<DIR, R>(T, C, L, s);
+            force<R>(s, P, Fx, Fy);
         }
-        double ux, uy;
-        velocity(f[cur], C.rho, Fx, Fy, ux, uy);
+        R ux, uy;
+        velocity<R>(f[cur], C.rho, Fx, Fy, ux, uy);
         const size_t row = (size_t)y * c.nx;
         if (MODE == kStep) {
-            collide(f[cur], C.rho, ux, uy, Fx, Fy, c);
+            collide<R>(f[cur], C.rho, ux, uy, Fx, Fy, P);
             if (interior) {
                 const size_t prow = (size_t)y * c.pitch;
 #pragma unroll
                 for (int i = 0; i < kQ; ++i)
                     __builtin_nontemporal_store(
-                        f[cur][i], (double *)((char *)(dst + i * c.plane + prow) + cols.o));
+                        (E)f[cur][i], (E *)((char *)(dst + i * c.plane + prow) + cols.o));
             }
         } else if (MODE == kMoments) {
             if (interior) {
                 const size_t cell = row + x;
-                if (fo.rho) fo.rho[cell] = C.rho;
-                if (fo.ux) fo.ux[cell] = ux;
-                if (fo.uy) fo.uy[cell] = uy;
-                if (fo.Fx) fo.Fx[cell] = Fx;
-                if (fo.Fy) fo.Fy[cell] = Fy;
-                if (fo.psi) fo.psi[cell] = C.o;
+                if (fo.rho) fo.rho[cell] = (double)C.rho;
+                if (fo.ux) fo.ux[cell] = (double)ux;
+                if (fo.uy) fo.uy[cell] = (double)uy;
+                if (fo.Fx) fo.Fx[cell] = (double)Fx;
+                if (fo.Fy) fo.Fy[cell] = (double)Fy;
+                if (fo.psi) fo.psi[cell] = (double)C.o;
             }
         } else {
             if (interior) {
                 const size_t cell = row + x;
+                const double r64 = (double)C.rho, ux64 = (double)ux, uy64 = (double)uy;
                 const double prev = rho_snap[cell];
-                rho_snap[cell] = C.rho;
-                acc[0] += C.rho;
-                acc[1] += C.rho * ux;
-                acc[2] += C.rho * uy;
-                acc[3] += fabs(C.rho - prev);
-                acc[4] += fabs(C.rho);
-                acc[5] = fmax(acc[5], sqrt(ux * ux + uy * uy));
+                rho_snap[cell] = r64;
+                acc[0] += r64;
+                acc[1] += r64 * ux64;
+                acc[2] += r64 * uy64;
+                acc[3] += fabs(r64 - prev);
+                acc[4] += fabs(r64);
+                acc[5] = fmax(acc[5], sqrt(ux64 * ux64 + uy64 * uy64));
             }
         }
     };
@@ -422,15 +480,19 @@ __device__ __forceinline__ void walk(const double *__restrict__ src, double *__r
     }, std::make_integer_sequence<int, K - 1>{});
 }
 
-template <int BX, int MODE, int PF, int FORCE>
-__global__ __launch_bounds__(BX) void sweep_kernel(const double *__restrict__ src,
-                                                   double *__restrict__ dst, Coeffs c, Tiles tl,
+template <int BX, int MODE, int PF, int FORCE, int ST>
+__global__ __launch_bounds__(BX) void sweep_kernel(const void *__restrict__ src_v,
+                                                   void *__restrict__ dst_v, Coeffs c, Tiles tl,
                                                    long long t,
                                                    unsigned long long *__restrict__ err,
                                                    Fields fo, double *__restrict__ rho_snap,
                                                    double *__restrict__ partials)
 {
-    __shared__ double lds[2 * BX];
+    using E = typename Store<ST>::E;
+    using R = typename Store<ST>::R;
+    const E *src = (const E *)src_v;
+    E *dst = (E *)dst_v;
+    __shared__ R lds[2 * BX];
     // Tiles are numbered row band by row band; workgroups are dealt to the 8
     // XCDs round-robin, so the strips of one band run side by side.
     const int tile = blockIdx.x;
@@ -448,16 +510,17 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const double *__restrict__ sr
     int x = xs - 1 + (active ? tx : 1);
     x = wrap_hi(wrap_lo(x, c.nx), c.nx);
     const int xm = wrap_lo(x - 1, c.nx), xp = wrap_hi(x + 1, c.nx);
-    const Cols cols{(uint32_t)x * 8u, (uint32_t)xm * 8u, (uint32_t)xp * 8u};
+    constexpr uint32_t es = sizeof(E);
+    const Cols cols{(uint32_t)x * es, (uint32_t)xm * es, (uint32_t)xp * es};
 
     double acc[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     unsigned long long bad = ~0ull;
     if (seg & 1)
-        walk<BX, MODE, -1, PF, FORCE>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
-                                      interior, lds, acc, bad);
+        walk<BX, MODE, -1, PF, FORCE, ST>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
+                                          interior, lds, acc, bad);
     else
-        walk<BX, MODE, +1, PF, FORCE>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
-                                      interior, lds, acc, bad);
+        walk<BX, MODE, +1, PF, FORCE, ST>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
+                                          interior, lds, acc, bad);
     if (bad != ~0ull) atomicMin(err, bad);
 
     if (MODE == kDiagnostics) {
@@ -500,12 +563,16 @@ __global__ __launch_bounds__(256) void reduce_partials(const double *__restrict_
     }
 }
 
-// Initial state f(0) = f^eq(rho0, u0) in pull storage: X_i(z) = f_i^eq at z + c_i.
-__global__ __launch_bounds__(256) void init_kernel(double *__restrict__ X, Coeffs c,
+// Initial state f(0) = f^eq(rho0, u0) in pull storage: X_i(z) holds
+// f_i^eq at z + c_i, stored as the deviation from w_i rho_ref, rounded once.
+template <int ST>
+__global__ __launch_bounds__(256) void init_kernel(void *__restrict__ X_v, Coeffs c,
                                                     const double *__restrict__ rho0,
                                                     const double *__restrict__ ux0,
                                                     const double *__restrict__ uy0)
 {
+    using E = typename Store<ST>::E;
+    E *X = (E *)X_v;
     const size_t n = (size_t)c.nx * c.ny;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -517,18 +584,21 @@ __global__ __launch_bounds__(256) void init_kernel(double *__restrict__ X, Coeff
         const int xx = wrap_hi(wrap_lo(x + cx[i], c.nx), c.nx);
         const int yy = wrap_hi(wrap_lo(y + cy[i], c.ny), c.ny);
         const size_t s = (size_t)yy * c.nx + xx;
-        X[i * c.plane + (size_t)y * c.pitch + x] =
-            feq_dir(i, rho0[s], ux0 ? ux0[s] : 0.0, uy0 ? uy0[s] : 0.0);
+        const double feq = feq_dir(i, rho0[s], ux0 ? ux0[s] : 0.0, uy0 ? uy0[s] : 0.0);
+        X[i * c.plane + (size_t)y * c.pitch + x] = (E)(feq - weight(i) * c.rho_ref);
     }
 }
 
-// Canonical f(t) <-> pull storage.  to_canonical: f_i(x) = X_i(x - c_i);
-// otherwise X_i(z) = f_i(z + c_i).  Canonical arrays are dense [9][ny][nx];
-// the storage has row pitch c.pitch and plane stride c.plane.
-__global__ __launch_bounds__(256) void permute_kernel(const double *__restrict__ in,
-                                                       double *__restrict__ out, Coeffs c,
+// Canonical f(t) <-> pull storage.  to_canonical: f_i(x) = w_i rho_ref +
+// X_i(x - c_i); otherwise X_i(z) = round(f_i(z + c_i) - w_i rho_ref).
+// Canonical arrays are dense FP64 [9][ny][nx]; the storage has row pitch
+// c.pitch and plane stride c.plane.
+template <int ST>
+__global__ __launch_bounds__(256) void permute_kernel(const void *__restrict__ in_v,
+                                                       void *__restrict__ out_v, Coeffs c,
                                                        int to_canonical)
 {
+    using E = typename Store<ST>::E;
     const size_t n = (size_t)c.nx * c.ny;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -537,14 +607,20 @@ __global__ __launch_bounds__(256) void permute_kernel(const double *__restrict__
     const int cy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
+        const double base = weight(i) * c.rho_ref;
         if (to_canonical) {
+            const E *in = (const E *)in_v;
+            double *out = (double *)out_v;
             const int xx = wrap_hi(wrap_lo(x - cx[i], c.nx), c.nx);
             const int yy = wrap_hi(wrap_lo(y - cy[i], c.ny), c.ny);
-            out[i * n + k] = in[i * c.plane + (size_t)yy * c.pitch + xx];
+            out[i * n + k] = base + (double)in[i * c.plane + (size_t)yy * c.pitch + xx];
         } else {
+            const double *in = (const double *)in_v;
+            E *out = (E *)out_v;
             const int xx = wrap_hi(wrap_lo(x + cx[i], c.nx), c.nx);
             const int yy = wrap_hi(wrap_lo(y + cy[i], c.ny), c.ny);
-            out[i * c.plane + (size_t)y * c.pitch + x] = in[i * n + (size_t)yy * c.nx + xx];
+            out[i * c.plane + (size_t)y * c.pitch + x] =
+                (E)(in[i * n + (size_t)yy * c.nx + xx] - base);
         }
     }
 }
@@ -565,7 +641,7 @@ struct lbm_handle {
     lbm_params p;
     Coeffs c;
     hipStream_t stream;
-    double *cur, *nxt;       // population buffers (pull storage)
+    void *cur, *nxt;         // population buffers (pull storage)
     double *rho_snap;        // density snapshot for Eq. SSC
     double *partials;        // per-tile diagnostics
     double *diag_out;        // kDiag doubles
@@ -583,31 +659,18 @@ struct Layout {
     size_t err, diag_out, partials, rho_snap, bufA, bufB, total, plane, pitch;
 };
 
-// Population storage padding.  Rows start on 128-byte boundaries (the row
-// pitch is nx rounded up to 16 elements; LBM_PAD_ROW=1 would also make it an
-// odd multiple of 16, which measured slower on 2048-wide lattices), and
-// consecutive planes are offset by 768 bytes beyond a 256-byte multiple so
-// that they do not all start at the same power-of-two boundary.
-#ifndef LBM_PAD_ROW
-#define LBM_PAD_ROW 0
-#endif
-#ifndef LBM_PAD_PLANE
-#define LBM_PAD_PLANE 1
-#endif
-size_t row_pitch(int nx)
-{
-    size_t p = round_up((size_t)nx, 16);
-    if (LBM_PAD_ROW && (p / 16) % 2 == 0) p += 16;
-    return p;
-}
-
+// Population storage.  Rows start on 128-byte boundaries (the pitch is nx
+// rounded up to 128 bytes), and consecutive planes are offset by 768 bytes
+// beyond a 256-byte multiple so that they do not all start on one
+// power-of-two boundary.  (Padding rows to an odd multiple of 128 bytes
+// measured slower on 2048-wide lattices.)
 Layout layout_for(const lbm_params *p)
 {
     Layout L;
     const size_t n = (size_t)p->nx * p->ny;
-    L.pitch = row_pitch(p->nx);
-    L.plane = round_up(L.pitch * p->ny, kAlign / sizeof(double));
-    if (LBM_PAD_PLANE) L.plane += 3 * kAlign / sizeof(double);
+    const size_t es = elem_size(p->storage);
+    L.pitch = round_up((size_t)p->nx, 128 / es);
+    L.plane = round_up(L.pitch * p->ny, kAlign / es) + 768 / es;
     size_t off = 0;
     L.err = off;
     off += kAlign;
@@ -618,9 +681,9 @@ Layout layout_for(const lbm_params *p)
     L.rho_snap = off;
     off += round_up(n * sizeof(double), kAlign);
     L.bufA = off;
-    off += kQ * L.plane * sizeof(double);
+    off += round_up(kQ * L.plane * es, kAlign);
     L.bufB = off;
-    off += kQ * L.plane * sizeof(double);
+    off += round_up(kQ * L.plane * es, kAlign);
     L.total = off;
     return L;
 }
@@ -642,7 +705,10 @@ bool params_valid(const lbm_params *p, std::string *why)
         return fail("EOS constants not finite");
     if (p->force_on != 0 && p->force_on != 1) return fail("force_on must be 0 or 1");
     if (p->m2_trace_alt != 0 && p->m2_trace_alt != 1) return fail("m2_trace_alt must be 0 or 1");
-    if (p->storage != LBM_STORE_F64) return fail("unsupported storage mode");
+    if (p->storage != LBM_STORE_F64 && p->storage != LBM_STORE_F32_SHIFTED &&
+        p->storage != LBM_STORE_F16_SHIFTED)
+        return fail("unknown storage mode");
+    if (!std::isfinite(p->rho_ref)) return fail("rho_ref not finite");
     return true;
 }
 
@@ -662,16 +728,22 @@ Coeffs make_coeffs(const lbm_params *p, size_t pitch, size_t plane)
     c.cSC = -6.0 * p->G;
     c.cA = 9.0 * p->G * (1.5 * p->epsilon - p->sigma + 1.0);
     c.cB = 9.0 * p->G * (p->sigma - 1.0);
+    c.rho_ref = p->storage == LBM_STORE_F64 ? 0.0 : p->rho_ref;
     c.force_on = p->force_on;
     c.trace_alt = p->m2_trace_alt;
+    c.storage = p->storage;
     return c;
 }
 
-bool make_tiles(int nx, int ny, int bx, int seg_rows, Tiles *tl)
+// Strip width alignment in columns: 128 bytes of FP64, 64 bytes of FP32 or FP16.
+int strip_align(int storage) { return storage == LBM_STORE_F16_SHIFTED ? 32 : 16; }
+
+bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl)
 {
     int w = bx - 2;
-    if (nx > w) w = w / 16 * 16;
+    if (nx > w) w = w / align * align;
     else w = nx;
+    if (w < 1) return false;
     tl->width = w;
     tl->nstrips = (nx + w - 1) / w;
     tl->nseg = (ny + seg_rows - 1) / seg_rows;
@@ -682,18 +754,21 @@ bool make_tiles(int nx, int ny, int bx, int seg_rows, Tiles *tl)
 }
 
 // Default launch shape: the workgroup width that wastes the fewest lanes on
-// ragged strips (ties to the wider one, up to 256 threads), then row segments
-// short enough for about 32 waves per CU on 256 CUs (more workgroups than fit
-// at once, so the hardware balances them), each segment at least 8 rows.
-// Measured on 2048 x 2048: (256 threads, 9 rows) is within 2 % of the best
-// shape of a sweep over 64..512 threads and 8..65 rows.
-void default_launch(int nx, int ny, int *bx_out, int *rows_out)
+// ragged strips (ties to 256 threads), then row segments short enough for
+// about 64 waves per CU on 256 CUs (20 for FP16 storage), each segment at
+// least 5 rows.  Many short segments keep more rows of loads in flight per
+// CU (each segment starts with a burst of three row loads); their halo rows
+// come back mostly from cache.  Measured on 2048 x 2048: FP64 and FP32 are
+// fastest at (256 threads, 5 rows), FP16 at (256, 17), in sweeps over
+// 128..512 threads and 2..65 rows.
+void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
 {
     int best = 256;
     double best_score = -1.0;
+    const int align = strip_align(storage);
     for (int bx = 64; bx <= 512; bx += 64) {
         Tiles tl;
-        make_tiles(nx, ny, bx, 1 << 30, &tl);
+        if (!make_tiles(nx, ny, bx, 1 << 30, align, &tl)) continue;
         const double eff = (double)nx / ((double)tl.nstrips * bx);
         const double score = eff - (bx > 256 ? 0.02 : 0.0) + (bx == 256 ? 0.02 : 0.0);
         if (score > best_score + 1e-12) {
@@ -702,12 +777,12 @@ void default_launch(int nx, int ny, int *bx_out, int *rows_out)
         }
     }
     Tiles tb;
-    make_tiles(nx, ny, best, 1 << 30, &tb);
-    const double target_waves = 256.0 * 32.0;
+    make_tiles(nx, ny, best, 1 << 30, align, &tb);
+    const double target_waves = 256.0 * (storage == LBM_STORE_F16_SHIFTED ? 20.0 : 64.0);
     int nseg = (int)std::ceil(target_waves / ((double)tb.nstrips * (best / 64)));
     nseg = std::max(1, std::min(nseg, ny));
     int rows = (ny + nseg - 1) / nseg;
-    rows = std::max(rows, std::min(8, ny));
+    rows = std::max(rows, std::min(5, ny));
     while ((long long)tb.nstrips * ((ny + rows - 1) / rows) > kMaxTiles)
         ++rows;
     *bx_out = best;
@@ -722,8 +797,8 @@ lbm_status dev_fail(lbm_handle *h, hipError_t e, const char *what)
     return LBM_ERR_DEVICE;
 }
 
-template <int MODE, int FORCE>
-hipError_t launch_sweep_f(lbm_handle *h, const double *src, double *dst, Fields fo)
+template <int MODE, int FORCE, int ST>
+hipError_t launch_sweep_t(lbm_handle *h, const void *src, void *dst, Fields fo)
 {
     const dim3 grid((unsigned)h->tiles.ntiles);
     const Coeffs &c = h->c;
@@ -731,9 +806,9 @@ hipError_t launch_sweep_f(lbm_handle *h, const double *src, double *dst, Fields 
     switch (h->bx) {
 #define LBM_CASE(BX)                                                                          \
     case BX:                                                                                  \
-        hipLaunchKernelGGL((sweep_kernel<BX, MODE, PF, FORCE>), grid, dim3(BX), 0, h->stream,   \
-                           src, dst, c, h->tiles, (long long)h->t, h->err, fo, h->rho_snap,   \
-                           h->partials);                                                      \
+        hipLaunchKernelGGL((sweep_kernel<BX, MODE, PF, FORCE, ST>), grid, dim3(BX), 0,         \
+                           h->stream, src, dst, c, h->tiles, (long long)h->t, h->err, fo,     \
+                           h->rho_snap, h->partials);                                         \
         break;
         LBM_CASE(64)
         LBM_CASE(128)
@@ -750,11 +825,63 @@ hipError_t launch_sweep_f(lbm_handle *h, const double *src, double *dst, Fields 
     return hipGetLastError();
 }
 
+template <int MODE, int FORCE>
+hipError_t launch_sweep_f(lbm_handle *h, const void *src, void *dst, Fields fo)
+{
+    switch (h->c.storage) {
+    case LBM_STORE_F64: return launch_sweep_t<MODE, FORCE, LBM_STORE_F64>(h, src, dst, fo);
+    case LBM_STORE_F32_SHIFTED:
+        return launch_sweep_t<MODE, FORCE, LBM_STORE_F32_SHIFTED>(h, src, dst, fo);
+    case LBM_STORE_F16_SHIFTED:
+        return launch_sweep_t<MODE, FORCE, LBM_STORE_F16_SHIFTED>(h, src, dst, fo);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int MODE>
-hipError_t launch_sweep(lbm_handle *h, const double *src, double *dst, Fields fo)
+hipError_t launch_sweep(lbm_handle *h, const void *src, void *dst, Fields fo)
 {
     return h->c.force_on ? launch_sweep_f<MODE, 1>(h, src, dst, fo)
                          : launch_sweep_f<MODE, 0>(h, src, dst, fo);
+}
+
+void launch_init(lbm_handle *h, unsigned blocks, const double *rho0, const double *ux0,
+                 const double *uy0)
+{
+    switch (h->c.storage) {
+    case LBM_STORE_F64:
+        hipLaunchKernelGGL(init_kernel<LBM_STORE_F64>, dim3(blocks), dim3(256), 0, h->stream,
+                           h->cur, h->c, rho0, ux0, uy0);
+        break;
+    case LBM_STORE_F32_SHIFTED:
+        hipLaunchKernelGGL(init_kernel<LBM_STORE_F32_SHIFTED>, dim3(blocks), dim3(256), 0,
+                           h->stream, h->cur, h->c, rho0, ux0, uy0);
+        break;
+    default:
+        hipLaunchKernelGGL(init_kernel<LBM_STORE_F16_SHIFTED>, dim3(blocks), dim3(256), 0,
+                           h->stream, h->cur, h->c, rho0, ux0, uy0);
+        break;
+    }
+}
+
+void launch_permute(lbm_handle *h, const void *in, void *out, int to_canonical)
+{
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    switch (h->c.storage) {
+    case LBM_STORE_F64:
+        hipLaunchKernelGGL(permute_kernel<LBM_STORE_F64>, grid, dim3(256), 0, h->stream, in,
+                           out, h->c, to_canonical);
+        break;
+    case LBM_STORE_F32_SHIFTED:
+        hipLaunchKernelGGL(permute_kernel<LBM_STORE_F32_SHIFTED>, grid, dim3(256), 0, h->stream,
+                           in, out, h->c, to_canonical);
+        break;
+    default:
+        hipLaunchKernelGGL(permute_kernel<LBM_STORE_F16_SHIFTED>, grid, dim3(256), 0, h->stream,
+                           in, out, h->c, to_canonical);
+        break;
+    }
 }
 
 lbm_status read_sticky(lbm_handle *h)
@@ -807,12 +934,13 @@ lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspac
     h->diag_out = (double *)(ws + L.diag_out);
     h->partials = (double *)(ws + L.partials);
     h->rho_snap = (double *)(ws + L.rho_snap);
-    h->cur = (double *)(ws + L.bufA);
-    h->nxt = (double *)(ws + L.bufB);
+    h->cur = (void *)(ws + L.bufA);
+    h->nxt = (void *)(ws + L.bufB);
     h->t = 0;
     h->sticky = LBM_OK;
-    default_launch(params->nx, params->ny, &h->bx, &h->seg_rows);
-    if (!make_tiles(params->nx, params->ny, h->bx, h->seg_rows, &h->tiles)) {
+    default_launch(params->nx, params->ny, params->storage, &h->bx, &h->seg_rows);
+    if (!make_tiles(params->nx, params->ny, h->bx, h->seg_rows, strip_align(params->storage),
+                    &h->tiles)) {
         delete h;
         return LBM_ERR_INVALID_ARG;
     }
@@ -820,8 +948,7 @@ lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspac
     const size_t n = (size_t)params->nx * params->ny;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(fill_u64, dim3(1), dim3(1), 0, h->stream, h->err, ~0ull);
-    hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, h->stream, h->cur, h->c, d_rho0,
-                       d_ux0, d_uy0);
+    launch_init(h, blocks, d_rho0, d_ux0, d_uy0);
     hipLaunchKernelGGL(copy_plane, dim3(blocks), dim3(256), 0, h->stream, d_rho0, h->rho_snap, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -882,9 +1009,7 @@ lbm_status lbm_diagnostics(lbm_handle *h, double out[6])
 lbm_status lbm_get_populations(lbm_handle *h, double *d_f)
 {
     if (!h || !d_f) return LBM_ERR_INVALID_ARG;
-    const size_t n = (size_t)h->p.nx * h->p.ny;
-    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
-                       h->cur, d_f, h->c, 1);
+    launch_permute(h, h->cur, d_f, 1);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return dev_fail(h, e, "copying populations out");
@@ -894,9 +1019,7 @@ lbm_status lbm_get_populations(lbm_handle *h, double *d_f)
 lbm_status lbm_set_populations(lbm_handle *h, const double *d_f, int64_t t)
 {
     if (!h || !d_f || t < 0) return LBM_ERR_INVALID_ARG;
-    const size_t n = (size_t)h->p.nx * h->p.ny;
-    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
-                       d_f, h->cur, h->c, 0);
+    launch_permute(h, d_f, h->cur, 0);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return dev_fail(h, e, "copying populations in");
@@ -909,19 +1032,17 @@ int64_t lbm_time(const lbm_handle *h) { return h ? h->t : -1; }
 lbm_status lbm_set_launch(lbm_handle *h, int32_t block_x, int32_t seg_rows)
 {
     if (!h) return LBM_ERR_INVALID_ARG;
-    int bx = h->bx, rows = h->seg_rows;
+    const int align = strip_align(h->p.storage);
     int dbx, drows;
-    default_launch(h->p.nx, h->p.ny, &dbx, &drows);
-    if (block_x != 0) bx = block_x;
-    else bx = dbx;
-    if (seg_rows != 0) rows = seg_rows;
-    else rows = drows;
+    default_launch(h->p.nx, h->p.ny, h->p.storage, &dbx, &drows);
+    const int bx = block_x != 0 ? block_x : dbx;
+    const int rows = seg_rows != 0 ? seg_rows : drows;
     if (bx < 64 || bx > 512 || bx % 64 != 0 || rows < 1) {
         h->last_error = "block_x must be a multiple of 64 in [64, 512] and seg_rows >= 1";
         return LBM_ERR_INVALID_ARG;
     }
     Tiles tl;
-    if (!make_tiles(h->p.nx, h->p.ny, bx, rows, &tl)) {
+    if (!make_tiles(h->p.nx, h->p.ny, bx, rows, align, &tl)) {
         h->last_error = "launch shape needs too many workgroups";
         return LBM_ERR_INVALID_ARG;
     }

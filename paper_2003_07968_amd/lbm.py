@@ -24,6 +24,8 @@ LBM_ERR_DEVICE = -3
 LBM_ERR_OOM = -4
 LBM_ERR_STATE = -5
 LBM_STORE_F64 = 0
+LBM_STORE_F32_SHIFTED = 1
+LBM_STORE_F16_SHIFTED = 2
 
 _ALIGN = 256
 

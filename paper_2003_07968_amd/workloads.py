@@ -62,9 +62,14 @@ def unit_cs_coexistence(tr: float):
     return UNIT_CS_MAXWELL[keys[-1]]
 
 
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+
+
 def params(nx, ny, tr=0.8, tau=1.0, G=-1.0, epsilon=1.73, sigma=1.0, eos="unit",
-           force_on=True, m2_trace_alt=False):
-    """A parameter dictionary in the field names of the library's parameter block."""
+           force_on=True, m2_trace_alt=False, storage="f64", rho_ref=0.0):
+    """A parameter dictionary in the field names of the library's parameter block.
+    storage is "f64", "f32" or "f16" (the last two store deviations from
+    w_i rho_ref)."""
     if eos == "unit":
         p = dict(UNIT_CS)
         T = tr * UNIT_CS_TC
@@ -75,8 +80,22 @@ def params(nx, ny, tr=0.8, tau=1.0, G=-1.0, epsilon=1.73, sigma=1.0, eos="unit",
         raise ValueError(eos)
     p.update(nx=int(nx), ny=int(ny), tau=float(tau), G=float(G), epsilon=float(epsilon),
              sigma=float(sigma), T=float(T), force_on=bool(force_on),
-             m2_trace_alt=bool(m2_trace_alt))
+             m2_trace_alt=bool(m2_trace_alt), storage=STORAGE[storage], rho_ref=float(rho_ref))
     return p
+
+
+def shift_reference(rho0, storage):
+    """Reference density rho_ref of the shifted storage modes.  FP32: the mean
+    density.  FP16: the smallest density, so that the gas phase of a
+    two-phase field is stored as small deviations (binary16 keeps 11
+    significant bits of each deviation; with the mean as reference the gas
+    populations would be stored as deviations several times larger than
+    themselves).  FP64 storage takes no reference."""
+    if storage in ("f64", 0):
+        return 0.0
+    if storage in ("f32", 1):
+        return float(np.mean(rho0))
+    return float(np.min(rho0))
 
 
 def noise(shape, seed, amplitude=1e-3):

@@ -9,7 +9,8 @@ def oracle_params(oracle, p):
     return oracle.make_params(p["nx"], p["ny"], tau=p["tau"], G=p["G"], epsilon=p["epsilon"],
                               sigma=p["sigma"],
                               eos=(p["eos_a"], p["eos_b"], p["eos_c"], p["eos_k"]), T=p["T"],
-                              force_on=p["force_on"], m2_trace_alt=p["m2_trace_alt"])
+                              force_on=p["force_on"], m2_trace_alt=p["m2_trace_alt"],
+                              storage=p.get("storage", 0), rho_ref=p.get("rho_ref", 0.0))
 
 
 def slab_bulk(rho):

@@ -137,3 +137,42 @@ def test_first_step_velocity_is_half_force(oracle):
     assert np.allclose(m["ux"], m["Fx"] / (2 * m["rho"]), atol=1e-17)
     assert np.allclose(m["uy"], m["Fy"] / (2 * m["rho"]), atol=1e-17)
     assert np.allclose(m["rho"], rho0, atol=0, rtol=1e-15)
+
+
+def test_storage_rounding_matches_ieee_formats(oracle):
+    # binary32 / binary16 rounding of the oracle against NumPy's conversions,
+    # over normal, subnormal, tie and overflow cases.
+    rng = np.random.default_rng(21)
+    vals = np.concatenate([
+        rng.standard_normal(2000) * 10.0 ** rng.uniform(-9, 5, 2000),
+        np.array([0.0, -0.0, 1.0, 65504.0, 65519.99, 65520.0, -65520.0, 1e6, 2.0 ** -24,
+                  2.0 ** -25, 3 * 2.0 ** -26, 2.0 ** -14, 1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11,
+                  -(1 + 2.0 ** -11), 2049.0, 2051.0]),
+    ])
+    for v in vals:
+        q16 = oracle.quantize(2, v)
+        with np.errstate(over="ignore"):
+            ref16 = float(np.float64(v).astype(np.float16))
+        assert q16 == ref16 or (np.isnan(q16) and np.isnan(ref16)), (v, q16, ref16)
+        assert oracle.quantize(1, v) == float(np.float32(v))
+        assert oracle.quantize(0, v) == v
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_reduced_storage_state_is_representable(oracle, storage):
+    # With reduced-precision storage every stored deviation is a value of the
+    # storage format (up to the FP64 rounding of w_i rho_ref + d when the state
+    # is rebuilt), at t = 0 and after steps; mass stays close.
+    p, rho0 = W.droplet_64(seed=1)
+    p["storage"], p["rho_ref"] = storage, float(rho0.mean())
+    P = oracle_params(oracle, p)
+    f = oracle.init(P, rho0)
+    oracle.step(P, f, 50)
+    d = f - WGT[:, None, None] * p["rho_ref"]
+    cast = np.float32 if storage == 1 else np.float16
+    err = np.abs(d.astype(cast).astype(np.float64) - d)
+    assert np.all(err <= 4 * np.finfo(np.float64).eps * np.abs(f))
+    # and the rounding is real: most deviations are not FP64-only values
+    assert np.mean(d != 0) > 0.5
+    m64 = W.droplet_64(seed=1)[1].sum()
+    assert abs(f.sum() / m64 - 1) < (1e-6 if storage == 1 else 3e-3)
