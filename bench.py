@@ -17,8 +17,12 @@ the same workload.
 --storage f32 / f16 runs the same workload with populations stored as FP32 /
 FP16 deviations from w_i rho_ref (FP32 arithmetic; 72 / 36 bytes per cell).
 
+--workload batch measures the batched form instead: 256 uneven droplet
+lattices in FP32-shifted storage (or --storage f16), one launch per step,
+against the same lattices stepped one by one in FP64.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--storage f64|f32|f16]
+                       [--storage f64|f32|f16] [--workload slab|batch]
        python bench.py --copy-calibration   (plain copy kernel for PMC scaling)
 """
 import argparse
@@ -96,6 +100,94 @@ def cpu_baseline(budget_s=12.0):
             "sample": f"one 2048x2048 slab (T_r=0.8), {steps} oracle steps, {el:.1f} s"}
 
 
+def run_batch(args):
+    """256 independent droplet lattices (sides log-uniform in [64, 512], T_r
+    U[0.55, 0.95], sigma U[1/8, 4], R0 U[0.15, 0.35] side, seed 6) stepped by
+    one batched launch per step with FP32-shifted storage, shape chosen by the
+    autotuner, 8-step HIP graphs replayed.  Beside it, the same lattices in
+    FP64 stepped one launch per lattice per step (the plain path)."""
+    import torch
+    from paper_2003_07968_amd import lbm
+    from paper_2003_07968_amd import workloads as W
+
+    storage = args.storage if args.storage != "f64" else "f32"
+    stream = torch.cuda.Stream()  # graphs cannot be captured on the null stream
+    with torch.cuda.stream(stream):
+        cases = W.batch_case(count=256, seed=6, storage=storage)
+        cells = sum(p["nx"] * p["ny"] for p, _ in cases)
+        lats = [lbm.Lattice(p, r) for p, r in cases]
+        batch = lbm.Batch(len(lats))
+        for lat in lats:
+            batch.add(lat)
+        bx, rows, us = batch.autotune()
+        err(f"batch of {len(lats)} lattices, {cells} cells; autotuned block {bx}, "
+            f"rows {rows}: {us:.1f} us/step")
+        batch.step(args.warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        batch.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gpu_ms = e0.elapsed_time(e1)
+        for lat in lats:
+            lat.sync()
+        err(f"timed {args.steps} batched steps: {gpu_ms:.2f} ms")
+
+        # the plain path on the same lattices: FP64 storage, one launch per
+        # lattice per step
+        seq_steps = max(8, args.steps // 10)
+        plain = []
+        for p, r in cases:
+            q = dict(p)
+            q["storage"], q["rho_ref"] = 0, 0.0
+            plain.append(lbm.Lattice(q, r))
+        for lat in plain:
+            lat.step(2)
+        torch.cuda.synchronize()
+        e2 = torch.cuda.Event(enable_timing=True)
+        e3 = torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        for _ in range(seq_steps):
+            for lat in plain:
+                lat.step(1)
+        e3.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = e2.elapsed_time(e3)
+        for lat in plain:
+            lat.sync()
+    mlups = cells * args.steps / (gpu_ms / 1e3) / 1e6
+    plain_mlups = cells * seq_steps / (plain_ms / 1e3) / 1e6
+    bpc = BYTES_PER_CELL[storage]
+    step_ms = gpu_ms / args.steps
+    achieved = bpc * cells / (step_ms / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": f"f32 arithmetic, {storage}-shifted storage", "data": "synthetic",
+        "config": {
+            "workload": "batch of 256 D2Q9 droplet lattices, sides log-uniform [64, 512], "
+                        "T_r U[0.55,0.95], sigma U[1/8,4], R0 U[0.15,0.35] side, seed 6; "
+                        "one batched launch per step, 8-step HIP graphs, autotuned shape",
+            "storage": storage, "lattices": len(lats), "cells": cells,
+            "bytes_per_cell_update": bpc, "launch_block_x_seg_rows": [bx, rows],
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "batch_step_kernel (plus a one-thread counter bump per step)",
+            "kernel_avg_ms": round(step_ms, 5),
+        },
+        "plain_fp64_sequential": {
+            "value": round(plain_mlups, 1), "unit": "MLUPS", "steps": seq_steps,
+            "speedup_of_batch": round(mlups / plain_mlups, 2),
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +196,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--storage", choices=sorted(BYTES_PER_CELL), default="f64")
+    ap.add_argument("--workload", choices=("slab", "batch"), default="slab")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -117,10 +210,14 @@ def main():
         copy_calibration()
         return
 
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.workload == "batch":
+        run_batch(args)
+        return
+
     from paper_2003_07968_amd import lbm
     from paper_2003_07968_amd import workloads as W
 
-    assert torch.cuda.is_available(), "bench.py needs the GPU"
     lats = []
     for tr in TEMPS:
         p, rho0 = W.slab_case(n=N, tr=tr)

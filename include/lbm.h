@@ -164,6 +164,58 @@ lbm_status lbm_set_launch(lbm_handle *h, int32_t block_x, int32_t seg_rows);
  * out[2] = workgroups per step. */
 lbm_status lbm_get_launch(const lbm_handle *h, int32_t out[3]);
 
+/* Pick the launch shape by measurement: time a few step launches for each
+ * candidate shape (workgroup widths 64..512, segment lengths 3..17 rows) and
+ * keep the fastest.  The timed launches write only the spare population
+ * buffer and are not counted as steps, so the state and t are unchanged.
+ * Synchronous; out (may be NULL) receives the chosen block_x, seg_rows and the
+ * measured microseconds per step. */
+lbm_status lbm_autotune(lbm_handle *h, double out[3]);
+
+/* ---- Batches: many lattices advanced together by one kernel launch per step ----
+ *
+ * A batch holds up to `capacity` handles created by lbm_init on the same HIP
+ * stream, all with the same storage mode and force_on, any sizes and any other
+ * parameters.  lbm_batch_step launches one kernel per time step covering every
+ * tile of every lattice (a workgroup finds its lattice in a device table), and
+ * replays a captured HIP graph of eight steps for every full eight steps of a
+ * call (not on the legacy null stream, which cannot be captured: there each
+ * step is launched on its own).  Each lattice keeps its own workspace, state,
+ * time counter and sticky error word, so lbm_moments, lbm_diagnostics,
+ * lbm_sync and checkpointing work per handle as before, and results are
+ * bitwise the same as stepping the handle alone.  A member may also be
+ * stepped or restarted on its own between batch calls: the next
+ * lbm_batch_step notices and rewrites the table (a synchronous upload), as it
+ * does after lbm_batch_add or lbm_batch_remove. */
+typedef struct lbm_batch lbm_batch;
+
+/* Device bytes of the batch table for `capacity` lattices. */
+size_t lbm_batch_workspace_bytes(int32_t capacity);
+
+/* Create an empty batch; d_workspace (>= lbm_batch_workspace_bytes, 256-byte
+ * aligned, caller-owned) holds the device table.  hip_stream must be the
+ * stream of the handles that will be added. */
+lbm_status lbm_batch_create(int32_t capacity, void *d_workspace, size_t workspace_bytes,
+                            void *hip_stream, lbm_batch **out);
+
+/* Add or remove a handle (the handle stays owned by the caller).  Adding fails
+ * with LBM_ERR_INVALID_ARG if the batch is full, the handle is already in it,
+ * or its storage mode, force_on or stream differ from the batch's. */
+lbm_status lbm_batch_add(lbm_batch *b, lbm_handle *h);
+lbm_status lbm_batch_remove(lbm_batch *b, lbm_handle *h);
+int32_t lbm_batch_size(const lbm_batch *b);
+
+/* Advance every lattice of the batch by nsteps (asynchronous). */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Choose the batch's workgroup width and segment length by timing candidate
+ * shapes on the batch as it is (state unchanged, as lbm_autotune).
+ * Synchronous; out (may be NULL): block_x, seg_rows, microseconds per step. */
+lbm_status lbm_batch_autotune(lbm_batch *b, double out[3]);
+
+/* Free the host batch object (the handles and the workspace are untouched). */
+void lbm_batch_destroy(lbm_batch *b);
+
 const char *lbm_status_string(lbm_status s);
 
 /* Text of the last error on this handle ("" if none).  Valid until the next

@@ -40,6 +40,7 @@
 #include <string>
 #include <type_traits>
 #include <utility>
+#include <vector>
 
 #include "lbm.h"
 
@@ -480,22 +481,19 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
     }, std::make_integer_sequence<int, K - 1>{});
 }
 
+// One tile of a sweep: strip `strip` of row band `seg` of one lattice.
 template <int BX, int MODE, int PF, int FORCE, int ST>
-__global__ __launch_bounds__(BX) void sweep_kernel(const void *__restrict__ src_v,
-                                                   void *__restrict__ dst_v, Coeffs c, Tiles tl,
-                                                   long long t,
-                                                   unsigned long long *__restrict__ err,
-                                                   Fields fo, double *__restrict__ rho_snap,
-                                                   double *__restrict__ partials)
+__device__ __forceinline__ void sweep_tile(const void *__restrict__ src_v, void *__restrict__ dst_v,
+                                           const Coeffs &c, const Tiles &tl, int tile,
+                                           long long t, unsigned long long *__restrict__ err,
+                                           const Fields &fo, double *__restrict__ rho_snap,
+                                           double *__restrict__ partials)
 {
     using E = typename Store<ST>::E;
     using R = typename Store<ST>::R;
     const E *src = (const E *)src_v;
     E *dst = (E *)dst_v;
     __shared__ R lds[2 * BX];
-    // Tiles are numbered row band by row band; workgroups are dealt to the 8
-    // XCDs round-robin, so the strips of one band run side by side.
-    const int tile = blockIdx.x;
     const int seg = tile / tl.nstrips;
     const int strip = tile - seg * tl.nstrips;
     const int xs = strip * tl.width;
@@ -537,6 +535,59 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const void *__restrict__ src_
         }
     }
 }
+
+// One sweep over one lattice: tiles are numbered row band by row band;
+// workgroups are dealt to the 8 XCDs round-robin, so the strips of one band
+// run side by side.
+template <int BX, int MODE, int PF, int FORCE, int ST>
+__global__ __launch_bounds__(BX) void sweep_kernel(const void *__restrict__ src,
+                                                   void *__restrict__ dst, Coeffs c, Tiles tl,
+                                                   long long t,
+                                                   unsigned long long *__restrict__ err,
+                                                   Fields fo, double *__restrict__ rho_snap,
+                                                   double *__restrict__ partials)
+{
+    sweep_tile<BX, MODE, PF, FORCE, ST>(src, dst, c, tl, blockIdx.x, t, err, fo, rho_snap,
+                                        partials);
+}
+
+// One lattice of a batch, as the batched step kernel sees it.
+struct BatchEntry {
+    Coeffs c;
+    Tiles tl;
+    const void *buf[2];       // population buffers; the first batched step reads buf[0]
+    unsigned long long *err;  // the lattice's sticky error word
+    long long t0;             // the lattice's step count before the batched steps
+    int tile0;                // its first tile in the batch grid
+};
+
+// One time step of every lattice of a batch: workgroup b runs tile
+// b - tile0 of the lattice whose tile range holds b (binary search over the
+// table, uniform per workgroup).  The step count since the table was written
+// is read from d_steps (so that a captured graph replays correctly); its
+// parity selects the source buffer.
+template <int BX, int PF, int FORCE, int ST>
+__global__ __launch_bounds__(BX) void batch_step_kernel(const BatchEntry *__restrict__ table,
+                                                        int nlat,
+                                                        const long long *__restrict__ d_steps)
+{
+    const long long steps = *d_steps;
+    const int parity = (int)(steps & 1);
+    int lo = 0, hi = nlat - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].tile0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchEntry &e = table[lo];
+    sweep_tile<BX, kStep, PF, FORCE, ST>(e.buf[parity], (void *)e.buf[parity ^ 1], e.c, e.tl,
+                                         b - e.tile0, e.t0 + steps, e.err, Fields{},
+                                         nullptr, nullptr);
+}
+
+__global__ void bump_counter(long long *p) { *p += 1; }
+__global__ void set_counter(long long *p, long long v) { *p = v; }
 
 // Second stage of the diagnostics: one workgroup sums the per-tile partials
 // in a fixed order.
@@ -653,7 +704,28 @@ struct lbm_handle {
     std::string last_error;
 };
 
+struct lbm_batch {
+    int capacity;
+    hipStream_t stream;
+    BatchEntry *d_table;
+    long long *d_steps;       // steps since the table was written
+    std::vector<lbm_handle *> members;
+    std::vector<BatchEntry> h_table;
+    std::vector<int64_t> t_at_upload;
+    std::vector<void *> cur_at_upload, nxt_at_upload;
+    long long steps_since_upload;
+    bool table_valid;
+    int storage, force_on;
+    int bx, rows;
+    int total_tiles;
+    hipGraphExec_t graph;     // kGraphSteps batched steps, valid with the table
+    bool graph_valid;
+    std::string last_error;
+};
+
 namespace {
+
+constexpr int kGraphSteps = 8;
 
 struct Layout {
     size_t err, diag_out, partials, rho_snap, bufA, bufB, total, plane, pitch;
@@ -738,7 +810,8 @@ Coeffs make_coeffs(const lbm_params *p, size_t pitch, size_t plane)
 // Strip width alignment in columns: 128 bytes of FP64, 64 bytes of FP32 or FP16.
 int strip_align(int storage) { return storage == LBM_STORE_F16_SHIFTED ? 32 : 16; }
 
-bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl)
+bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl,
+                long long limit = kMaxTiles)
 {
     int w = bx - 2;
     if (nx > w) w = w / align * align;
@@ -748,7 +821,7 @@ bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl)
     tl->nstrips = (nx + w - 1) / w;
     tl->nseg = (ny + seg_rows - 1) / seg_rows;
     const long long nt = (long long)tl->nstrips * tl->nseg;
-    if (nt > kMaxTiles) return false;
+    if (nt > limit) return false;
     tl->ntiles = (int)nt;
     return true;
 }
@@ -903,6 +976,171 @@ lbm_status read_sticky(lbm_handle *h)
     return h->sticky;
 }
 
+
+template <int FORCE, int ST>
+hipError_t launch_batch_t(lbm_batch *b)
+{
+    const dim3 grid((unsigned)b->total_tiles);
+    const int nlat = (int)b->members.size();
+    switch (b->bx) {
+#define LBM_CASE(BX)                                                                          \
+    case BX:                                                                                  \
+        hipLaunchKernelGGL((batch_step_kernel<BX, kPrefetch, FORCE, ST>), grid, dim3(BX), 0,   \
+                           b->stream, b->d_table, nlat, b->d_steps);                          \
+        break;
+        LBM_CASE(64)
+        LBM_CASE(128)
+        LBM_CASE(192)
+        LBM_CASE(256)
+        LBM_CASE(320)
+        LBM_CASE(384)
+        LBM_CASE(448)
+        LBM_CASE(512)
+#undef LBM_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int FORCE>
+hipError_t launch_batch_f(lbm_batch *b)
+{
+    switch (b->storage) {
+    case LBM_STORE_F64: return launch_batch_t<FORCE, LBM_STORE_F64>(b);
+    case LBM_STORE_F32_SHIFTED: return launch_batch_t<FORCE, LBM_STORE_F32_SHIFTED>(b);
+    case LBM_STORE_F16_SHIFTED: return launch_batch_t<FORCE, LBM_STORE_F16_SHIFTED>(b);
+    }
+    return hipErrorInvalidValue;
+}
+
+// One batched step (the kernel only; the caller bumps the step counter).
+hipError_t launch_batch(lbm_batch *b)
+{
+    return b->force_on ? launch_batch_f<1>(b) : launch_batch_f<0>(b);
+}
+
+// Average duration in microseconds of `reps` calls of fn on `stream`, after
+// one untimed call.  Returns a negative value on a HIP error.
+template <class Fn>
+double time_launches(hipStream_t stream, int reps, Fn &&fn)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0;
+    }
+    double us = -1.0;
+    if (fn() == hipSuccess && hipEventRecord(e0, stream) == hipSuccess) {
+        bool ok = true;
+        for (int r = 0; r < reps && ok; ++r)
+            ok = fn() == hipSuccess;
+        float ms = 0.0f;
+        if (ok && hipEventRecord(e1, stream) == hipSuccess &&
+            hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            us = 1e3 * ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return us;
+}
+
+const int kTuneWidths[] = {64, 128, 192, 256, 320, 384, 512};
+const int kTuneRows[] = {3, 5, 7, 9, 13, 17};
+
+// Rebuild and upload the batch table for the current members and shape.
+// Synchronous (the host staging vector is reused by the next upload).
+lbm_status batch_upload(lbm_batch *b)
+{
+    b->h_table.clear();
+    b->t_at_upload.clear();
+    b->cur_at_upload.clear();
+    b->nxt_at_upload.clear();
+    int tile0 = 0;
+    const int align = strip_align(b->storage);
+    for (lbm_handle *h : b->members) {
+        BatchEntry e;
+        e.c = h->c;
+        if (!make_tiles(h->p.nx, h->p.ny, b->bx, std::min(b->rows, h->p.ny), align, &e.tl,
+                        1ll << 30)) {
+            b->last_error = "launch shape does not fit a lattice of the batch";
+            return LBM_ERR_INVALID_ARG;
+        }
+        e.buf[0] = h->cur;
+        e.buf[1] = h->nxt;
+        e.err = h->err;
+        e.t0 = h->t;
+        e.tile0 = tile0;
+        tile0 += e.tl.ntiles;
+        b->h_table.push_back(e);
+        b->t_at_upload.push_back(h->t);
+        b->cur_at_upload.push_back(h->cur);
+        b->nxt_at_upload.push_back(h->nxt);
+    }
+    b->total_tiles = tile0;
+    hipError_t e = hipSuccess;
+    if (!b->h_table.empty())
+        e = hipMemcpyAsync(b->d_table, b->h_table.data(), b->h_table.size() * sizeof(BatchEntry),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(set_counter, dim3(1), dim3(1), 0, b->stream, b->d_steps, 0ll);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        b->last_error = std::string("uploading the batch table: ") + hipGetErrorString(e);
+        return LBM_ERR_DEVICE;
+    }
+    if (b->graph_valid) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph_valid = false;
+    }
+    b->steps_since_upload = 0;
+    b->table_valid = true;
+    return LBM_OK;
+}
+
+// True when the table no longer describes the members: membership changed,
+// or some member was stepped or restarted outside the batch since the table
+// was written.
+bool batch_stale(const lbm_batch *b)
+{
+    if (!b->table_valid || b->t_at_upload.size() != b->members.size()) return true;
+    const bool odd = (b->steps_since_upload & 1) != 0;
+    for (size_t k = 0; k < b->members.size(); ++k) {
+        const lbm_handle *h = b->members[k];
+        if (h->t != b->t_at_upload[k] + b->steps_since_upload) return true;
+        if (h->cur != (odd ? b->nxt_at_upload[k] : b->cur_at_upload[k])) return true;
+    }
+    return false;
+}
+
+// Capture kGraphSteps batched steps (kernel + counter bump each) in a graph.
+hipError_t batch_capture(lbm_batch *b)
+{
+    hipGraph_t g;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < kGraphSteps && le == hipSuccess; ++k) {
+        le = launch_batch(b);
+        if (le == hipSuccess) {
+            hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->stream, b->d_steps);
+            le = hipGetLastError();
+        }
+    }
+    e = hipStreamEndCapture(b->stream, &g);
+    if (le != hipSuccess) {
+        if (e == hipSuccess) (void)hipGraphDestroy(g);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e == hipSuccess) b->graph_valid = true;
+    return e;
+}
 }  // namespace
 
 extern "C" {
@@ -1059,6 +1297,202 @@ lbm_status lbm_get_launch(const lbm_handle *h, int32_t out[3])
     out[1] = h->seg_rows;
     out[2] = h->tiles.ntiles;
     return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_handle *h, double out[3])
+{
+    if (!h) return LBM_ERR_INVALID_ARG;
+    const int align = strip_align(h->p.storage);
+    const int bx0 = h->bx, rows0 = h->seg_rows;
+    const Tiles tl0 = h->tiles;
+    double best = 1e300;
+    int best_bx = bx0, best_rows = rows0;
+    for (int bx : kTuneWidths)
+        for (int rows : kTuneRows) {
+            Tiles tl;
+            if (!make_tiles(h->p.nx, h->p.ny, bx, std::min(rows, h->p.ny), align, &tl)) continue;
+            h->bx = bx;
+            h->seg_rows = std::min(rows, h->p.ny);
+            h->tiles = tl;
+            // cur -> nxt without swapping: the state is not advanced
+            const double us = time_launches(h->stream, 3, [&] {
+                return launch_sweep<kStep>(h, h->cur, h->nxt, Fields{});
+            });
+            if (us < 0) {
+                h->bx = bx0;
+                h->seg_rows = rows0;
+                h->tiles = tl0;
+                return dev_fail(h, hipGetLastError(), "timing a launch shape");
+            }
+            if (us < best) {
+                best = us;
+                best_bx = bx;
+                best_rows = h->seg_rows;
+            }
+        }
+    make_tiles(h->p.nx, h->p.ny, best_bx, best_rows, align, &h->tiles);
+    h->bx = best_bx;
+    h->seg_rows = best_rows;
+    if (out) {
+        out[0] = best_bx;
+        out[1] = best_rows;
+        out[2] = best;
+    }
+    return LBM_OK;
+}
+
+size_t lbm_batch_workspace_bytes(int32_t capacity)
+{
+    if (capacity < 1) return 0;
+    return round_up((size_t)capacity * sizeof(BatchEntry), kAlign) + kAlign;
+}
+
+lbm_status lbm_batch_create(int32_t capacity, void *d_workspace, size_t workspace_bytes,
+                            void *hip_stream, lbm_batch **out)
+{
+    if (!out) return LBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (capacity < 1 || !d_workspace || workspace_bytes < lbm_batch_workspace_bytes(capacity) ||
+        ((uintptr_t)d_workspace) % kAlign != 0)
+        return LBM_ERR_INVALID_ARG;
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_ERR_OOM;
+    b->capacity = capacity;
+    b->stream = (hipStream_t)hip_stream;
+    b->d_table = (BatchEntry *)d_workspace;
+    b->d_steps =
+        (long long *)((char *)d_workspace + round_up((size_t)capacity * sizeof(BatchEntry), kAlign));
+    b->steps_since_upload = 0;
+    b->table_valid = false;
+    b->storage = -1;
+    b->force_on = -1;
+    b->bx = 256;
+    b->rows = 5;
+    b->total_tiles = 0;
+    b->graph_valid = false;
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_add(lbm_batch *b, lbm_handle *h)
+{
+    if (!b || !h) return LBM_ERR_INVALID_ARG;
+    if ((int)b->members.size() >= b->capacity) {
+        b->last_error = "batch is full";
+        return LBM_ERR_INVALID_ARG;
+    }
+    for (lbm_handle *m : b->members)
+        if (m == h) return LBM_ERR_INVALID_ARG;
+    if (!b->members.empty() &&
+        (h->p.storage != b->storage || h->p.force_on != b->force_on || h->stream != b->stream))
+        return LBM_ERR_INVALID_ARG;
+    if (b->members.empty()) {
+        if (h->stream != b->stream) return LBM_ERR_INVALID_ARG;
+        b->storage = h->p.storage;
+        b->force_on = h->p.force_on;
+    }
+    b->members.push_back(h);
+    b->table_valid = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_remove(lbm_batch *b, lbm_handle *h)
+{
+    if (!b || !h) return LBM_ERR_INVALID_ARG;
+    for (size_t k = 0; k < b->members.size(); ++k)
+        if (b->members[k] == h) {
+            b->members.erase(b->members.begin() + (long)k);
+            b->table_valid = false;
+            return LBM_OK;
+        }
+    return LBM_ERR_INVALID_ARG;
+}
+
+int32_t lbm_batch_size(const lbm_batch *b) { return b ? (int32_t)b->members.size() : -1; }
+
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return LBM_ERR_INVALID_ARG;
+    if (b->members.empty() || nsteps == 0) return LBM_OK;
+    if (batch_stale(b)) {
+        const lbm_status st = batch_upload(b);
+        if (st != LBM_OK) return st;
+    }
+    int64_t done = 0;
+    // the legacy null stream cannot be captured: there every step is launched
+    // on its own
+    const bool graphs = b->stream != nullptr;
+    if (graphs && nsteps >= kGraphSteps && !b->graph_valid) {
+        const hipError_t e = batch_capture(b);
+        if (e != hipSuccess) {
+            b->last_error = std::string("capturing the batch graph: ") + hipGetErrorString(e);
+            return LBM_ERR_DEVICE;
+        }
+    }
+    while (graphs && nsteps - done >= kGraphSteps) {
+        const hipError_t e = hipGraphLaunch(b->graph, b->stream);
+        if (e != hipSuccess) {
+            b->last_error = std::string("launching the batch graph: ") + hipGetErrorString(e);
+            return LBM_ERR_DEVICE;
+        }
+        done += kGraphSteps;
+    }
+    for (; done < nsteps; ++done) {
+        hipError_t e = launch_batch(b);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->stream, b->d_steps);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) {
+            b->last_error = std::string("launching a batched step: ") + hipGetErrorString(e);
+            return LBM_ERR_DEVICE;
+        }
+    }
+    b->steps_since_upload += nsteps;
+    for (lbm_handle *h : b->members) {
+        h->t += nsteps;
+        if (nsteps & 1) std::swap(h->cur, h->nxt);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch *b, double out[3])
+{
+    if (!b) return LBM_ERR_INVALID_ARG;
+    if (b->members.empty()) return LBM_OK;
+    const int bx0 = b->bx, rows0 = b->rows;
+    double best = 1e300;
+    int best_bx = bx0, best_rows = rows0;
+    for (int bx : kTuneWidths)
+        for (int rows : kTuneRows) {
+            b->bx = bx;
+            b->rows = rows;
+            if (batch_upload(b) != LBM_OK) continue;
+            // the step counter stays 0: every timed launch reads the same buffers
+            const double us = time_launches(b->stream, 3, [&] { return launch_batch(b); });
+            if (us >= 0 && us < best) {
+                best = us;
+                best_bx = bx;
+                best_rows = rows;
+            }
+        }
+    b->bx = best_bx;
+    b->rows = best_rows;
+    const lbm_status st = batch_upload(b);
+    if (st != LBM_OK) return st;
+    if (out) {
+        out[0] = best_bx;
+        out[1] = best_rows;
+        out[2] = best;
+    }
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return;
+    if (b->graph_valid) (void)hipGraphExecDestroy(b->graph);
+    delete b;
 }
 
 const char *lbm_status_string(lbm_status s)

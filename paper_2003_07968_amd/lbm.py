@@ -91,14 +91,37 @@ def _load():
         lib.lbm_last_error.restype = ctypes.c_char_p
         lib.lbm_destroy.argtypes = [H]
         lib.lbm_destroy.restype = None
+        D3 = ctypes.POINTER(ctypes.c_double)
+        lib.lbm_autotune.argtypes = [H, D3]
+        lib.lbm_autotune.restype = ctypes.c_int
+        B = ctypes.c_void_p
+        lib.lbm_batch_workspace_bytes.argtypes = [ctypes.c_int32]
+        lib.lbm_batch_workspace_bytes.restype = ctypes.c_size_t
+        lib.lbm_batch_create.argtypes = [ctypes.c_int32, _VP, ctypes.c_size_t, _VP,
+                                         ctypes.POINTER(B)]
+        lib.lbm_batch_create.restype = ctypes.c_int
+        lib.lbm_batch_add.argtypes = [B, H]
+        lib.lbm_batch_add.restype = ctypes.c_int
+        lib.lbm_batch_remove.argtypes = [B, H]
+        lib.lbm_batch_remove.restype = ctypes.c_int
+        lib.lbm_batch_size.argtypes = [B]
+        lib.lbm_batch_size.restype = ctypes.c_int32
+        lib.lbm_batch_step.argtypes = [B, ctypes.c_int64]
+        lib.lbm_batch_step.restype = ctypes.c_int
+        lib.lbm_batch_autotune.argtypes = [B, D3]
+        lib.lbm_batch_autotune.restype = ctypes.c_int
+        lib.lbm_batch_destroy.argtypes = [B]
+        lib.lbm_batch_destroy.restype = None
         _lib = lib
     return _lib
 
 
 EXPORTED = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_sync", "lbm_moments",
             "lbm_diagnostics", "lbm_get_populations", "lbm_set_populations", "lbm_time",
-            "lbm_set_launch", "lbm_get_launch", "lbm_status_string", "lbm_last_error",
-            "lbm_destroy")
+            "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_batch_workspace_bytes",
+            "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
+            "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_destroy", "lbm_status_string",
+            "lbm_last_error", "lbm_destroy")
 
 
 def make_params(p: dict) -> lbm_params:
@@ -184,6 +207,58 @@ def lbm_get_launch(h):
     return tuple(out)
 
 
+def lbm_autotune(h):
+    out = (ctypes.c_double * 3)()
+    _check(h, _load().lbm_autotune(h, out))
+    return int(out[0]), int(out[1]), float(out[2])
+
+
+def lbm_batch_workspace_bytes(capacity):
+    return _load().lbm_batch_workspace_bytes(int(capacity))
+
+
+def lbm_batch_create(capacity, workspace, stream=None):
+    b = ctypes.c_void_p()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = _load().lbm_batch_create(int(capacity), ctypes.c_void_p(workspace.data_ptr()),
+                                  workspace.numel() * workspace.element_size(),
+                                  ctypes.c_void_p(s.cuda_stream), ctypes.byref(b))
+    if st != LBM_OK:
+        raise LbmError(st)
+    return b.value
+
+
+def _check_b(st):
+    if st != LBM_OK:
+        raise LbmError(st)
+
+
+def lbm_batch_add(b, h):
+    _check_b(_load().lbm_batch_add(b, h))
+
+
+def lbm_batch_remove(b, h):
+    _check_b(_load().lbm_batch_remove(b, h))
+
+
+def lbm_batch_size(b):
+    return _load().lbm_batch_size(b)
+
+
+def lbm_batch_step(b, nsteps):
+    _check_b(_load().lbm_batch_step(b, int(nsteps)))
+
+
+def lbm_batch_autotune(b):
+    out = (ctypes.c_double * 3)()
+    _check_b(_load().lbm_batch_autotune(b, out))
+    return int(out[0]), int(out[1]), float(out[2])
+
+
+def lbm_batch_destroy(b):
+    _load().lbm_batch_destroy(b)
+
+
 def lbm_last_error(h):
     return _load().lbm_last_error(h).decode()
 
@@ -254,9 +329,51 @@ class Lattice:
     def launch(self):
         return lbm_get_launch(self.handle)
 
+    def autotune(self):
+        return lbm_autotune(self.handle)
+
     def close(self):
         if self.handle:
             lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A group of Lattice objects advanced together, one kernel launch per step."""
+
+    def __init__(self, capacity, device="cuda", stream=None):
+        self.workspace = torch.empty(lbm_batch_workspace_bytes(capacity), dtype=torch.uint8,
+                                     device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.handle = lbm_batch_create(capacity, self.workspace, self.stream)
+        self.members = []
+
+    def add(self, lat):
+        lbm_batch_add(self.handle, lat.handle)
+        self.members.append(lat)
+
+    def remove(self, lat):
+        lbm_batch_remove(self.handle, lat.handle)
+        self.members.remove(lat)
+
+    def __len__(self):
+        return lbm_batch_size(self.handle)
+
+    def step(self, n=1):
+        lbm_batch_step(self.handle, n)
+
+    def autotune(self):
+        return lbm_batch_autotune(self.handle)
+
+    def close(self):
+        if self.handle:
+            lbm_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -183,3 +183,24 @@ def ellipse_case(n=1024, tr=0.7, tau=1.0, seed=8, r_max=160.0, r_min=120.0):
     rg, rl = unit_cs_coexistence(tr)
     rho0 = ellipse(n, n, r_max, r_min, rl, rg, 2.0) + noise((n, n), seed)
     return p, rho0
+
+
+def batch_case(count=256, seed=6, storage="f32", side_range=(64, 512)):
+    """A batch of independent square droplet lattices: side = round(exp U(ln 64,
+    ln 512)), T_r ~ U[0.55, 0.95], sigma ~ U[1/8, 4] (the range of Table DVT),
+    R0 = U[0.15, 0.35] side, W = 2, tau = 1, eps = 1.73, U(+-1e-3) noise, the
+    given storage.  Returns a list of (params, rho0)."""
+    rng = np.random.default_rng(seed)
+    lo, hi = side_range
+    out = []
+    for k in range(count):
+        side = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        tr = float(rng.uniform(0.55, 0.95))
+        sigma = float(rng.uniform(0.125, 4.0))
+        r0 = float(rng.uniform(0.15, 0.35)) * side
+        p = params(side, side, tr=tr, tau=1.0, sigma=sigma, storage=storage)
+        rg, rl = unit_cs_coexistence(tr)
+        rho0 = droplet(side, side, r0, rl, rg, 2.0) + noise((side, side), seed * 100003 + k)
+        p["rho_ref"] = shift_reference(rho0, storage)
+        out.append((p, rho0))
+    return out
