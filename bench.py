@@ -21,8 +21,12 @@ FP16 deviations from w_i rho_ref (FP32 arithmetic; 72 / 36 bytes per cell).
 lattices in FP32-shifted storage (or --storage f16), one launch per step,
 against the same lattices stepped one by one in FP64.
 
+--workload serve runs a Poisson stream of jobs through the continuous-batching
+server (FP32- and FP16-shifted) and reports p50/p99 time-to-result beside the
+same jobs run one after another on the plain FP64 path.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--storage f64|f32|f16] [--workload slab|batch]
+                       [--storage f64|f32|f16] [--workload slab|batch|serve] [--jobs J]
        python bench.py --copy-calibration   (plain copy kernel for PMC scaling)
 """
 import argparse
@@ -188,6 +192,131 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _percentiles(x):
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    return {"p50_s": round(float(np.percentile(x, 50)), 4),
+            "p99_s": round(float(np.percentile(x, 99)), 4),
+            "mean_s": round(float(x.mean()), 4)}
+
+
+def serve_stream(jobs, arrivals, storage, arena_bytes, quantum):
+    """Run the jobs through the serving loop in real time: each is submitted at
+    its arrival time; returns time-to-result per job, the makespan and the
+    server's counters."""
+    import numpy as np
+    from paper_2003_07968_amd import lbm
+    srv = lbm.Server(arena_bytes=arena_bytes, max_resident=128, quantum=quantum, max_bypass=16)
+    order = np.argsort(arrivals, kind="stable")
+    done_at, ids = {}, {}
+    nxt = 0
+    t0 = time.perf_counter()
+    while len(done_at) < len(jobs):
+        now = time.perf_counter() - t0
+        while nxt < len(jobs) and arrivals[order[nxt]] <= now:
+            k = int(order[nxt])
+            p, rho0, n = jobs[k]
+            q = dict(p)
+            q["storage"] = {"f32": 1, "f16": 2}[storage]
+            ids[srv.submit(q, rho0, n)] = k
+            nxt += 1
+        st = srv.stats()
+        if st["queued"] == 0 and st["resident"] == 0:
+            if nxt < len(jobs):
+                time.sleep(max(0.0, arrivals[order[nxt]] - (time.perf_counter() - t0)))
+            continue
+        srv.advance()
+        t = time.perf_counter() - t0
+        for job, status, rho, f in srv.poll():
+            if status != lbm.LBM_OK:
+                raise RuntimeError(f"job {job} failed with status {status}")
+            done_at[ids[job]] = t
+    stats = srv.stats()
+    srv.close()
+    ttr = [done_at[k] - arrivals[k] for k in range(len(jobs))]
+    return ttr, max(done_at.values()), stats
+
+
+def run_serve(args):
+    """Continuous batching of a Poisson stream of jobs (sides log-uniform in
+    [64, 1024], steps U[2000, 50000], droplet or slab, seed 7) in FP32- and
+    FP16-shifted storage, against running the same jobs one after another with
+    the plain FP64 path (first come, first served)."""
+    import numpy as np
+    import torch
+    from paper_2003_07968_amd import lbm
+    from paper_2003_07968_amd import workloads as W
+
+    jobs = W.serve_case(count=args.jobs, seed=7, storage="f32")
+    work = np.array([p["nx"] * p["ny"] * n for p, _, n in jobs], dtype=np.float64)
+    arena = 48 << 30
+    quantum = 128
+
+    # capacity: the first 16 jobs, 2000 steps each, all submitted at once
+    cal = [(p, r, 2000) for p, r, _ in jobs[:16]]
+    _, span, st = serve_stream(cal, np.zeros(len(cal)), "f32", arena, quantum)
+    capacity = st["cell_steps"] / span
+    rate = 0.8 * capacity / work.mean()
+    arrivals = W.poisson_arrivals(len(jobs), rate, seed=7)
+    err(f"{len(jobs)} jobs, {work.sum():.3e} cell updates; capacity {capacity / 1e6:.0f} MLUPS "
+        f"-> arrival rate {rate:.2f} jobs/s")
+
+    served = {}
+    for storage in ("f32", "f16"):
+        ttr, span, st = serve_stream(jobs, arrivals, storage, arena, quantum)
+        served[storage] = dict(_percentiles(ttr), mlups=round(st["cell_steps"] / span / 1e6, 1),
+                               makespan_s=round(span, 3), rounds=st["rounds"],
+                               arena_peak_bytes=st["arena_peak"])
+        err(f"served {storage}: {served[storage]}")
+
+    # sequential FP64: each job alone (init, steps, density to the host), its
+    # service time measured; first-come-first-served completion times follow
+    stream = torch.cuda.Stream()
+    service = np.zeros(len(jobs))
+    with torch.cuda.stream(stream):
+        for k, (p, rho0, n) in enumerate(jobs):
+            q = dict(p)
+            q["storage"], q["rho_ref"] = 0, 0.0
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            lat = lbm.Lattice(q, rho0)
+            lat.step(n)
+            lat.moments()["rho"].cpu()
+            lat.sync()
+            service[k] = time.perf_counter() - t
+            del lat
+    finish, ttr_seq = 0.0, []
+    for k in np.argsort(arrivals, kind="stable"):
+        finish = max(finish, arrivals[k]) + service[k]
+        ttr_seq.append(finish - arrivals[k])
+    seq = dict(_percentiles(ttr_seq), mlups=round(work.sum() / service.sum() / 1e6, 1),
+               makespan_s=round(finish, 3))
+    err(f"sequential fp64: {seq}")
+
+    out = {
+        "metric": METRIC, "value": served["f32"]["mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 arithmetic, f32-shifted storage", "data": "synthetic",
+        "config": {
+            "workload": f"serving stream of {len(jobs)} D2Q9 jobs, Poisson arrivals at "
+                        f"{rate:.2f}/s (0.8 x measured capacity), sides log-uniform "
+                        "[64, 1024], steps U[2000, 50000], droplet or slab, T_r U[0.55,0.95], "
+                        "sigma U[1/8,4], seed 7; continuous batching, HBM-footprint admission",
+            "jobs": len(jobs), "cell_updates": float(work.sum()), "arrival_rate_per_s": rate,
+            "capacity_mlups": round(capacity / 1e6, 1), "quantum_steps": quantum,
+            "arena_bytes": arena,
+        },
+        "time_to_result": {"served_f32": served["f32"], "served_f16": served["f16"],
+                           "sequential_fp64": seq,
+                           "p99_speedup_f32_vs_sequential_fp64":
+                               round(seq["p99_s"] / served["f32"]["p99_s"], 2),
+                           "p50_speedup_f32_vs_sequential_fp64":
+                               round(seq["p50_s"] / served["f32"]["p50_s"], 2)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,7 +325,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--storage", choices=sorted(BYTES_PER_CELL), default="f64")
-    ap.add_argument("--workload", choices=("slab", "batch"), default="slab")
+    ap.add_argument("--workload", choices=("slab", "batch", "serve"), default="slab")
+    ap.add_argument("--jobs", type=int, default=64, help="jobs in the serving stream")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -213,6 +343,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
 
     from paper_2003_07968_amd import lbm

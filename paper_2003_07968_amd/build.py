@@ -1,4 +1,5 @@
-"""Compile the HIP library (csrc/lbm.hip -> liblbm.so) for gfx950 with hipcc.
+"""Compile the HIP library (csrc/lbm.hip and the host-side serving loop
+csrc/server.cpp -> liblbm.so) for gfx950 with hipcc.
 
 Run as `python -m paper_2003_07968_amd.build`.  The library is built in-tree
 so that it travels with the source tree.
@@ -10,6 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "lbm.hip")
+SOURCES = [SRC, os.path.join(HERE, "csrc", "server.cpp")]
 LIB = os.path.join(HERE, "liblbm.so")
 INCLUDE = os.path.join(ROOT, "include")
 
@@ -33,7 +35,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc(), *FLAGS, "-o", tmp, *SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

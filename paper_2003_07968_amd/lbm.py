@@ -12,6 +12,7 @@ Arrays: fields are torch.float64 CUDA tensors of shape (ny, nx), populations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,6 +41,19 @@ class lbm_params(ctypes.Structure):
         ("force_on", ctypes.c_int32), ("m2_trace_alt", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("rho_ref", ctypes.c_double),
     ]
+
+
+class lbm_server_config(ctypes.Structure):
+    _fields_ = [("max_resident", ctypes.c_int32), ("quantum", ctypes.c_int32),
+                ("max_bypass", ctypes.c_int32)]
+
+
+class lbm_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int32), ("resident", ctypes.c_int32),
+                ("rounds", ctypes.c_int64), ("cell_steps", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
+                ("arena_peak", ctypes.c_size_t)]
 
 
 class LbmError(RuntimeError):
@@ -112,6 +126,25 @@ def _load():
         lib.lbm_batch_autotune.restype = ctypes.c_int
         lib.lbm_batch_destroy.argtypes = [B]
         lib.lbm_batch_destroy.restype = None
+        S = ctypes.c_void_p
+        DP = ctypes.POINTER(ctypes.c_double)
+        lib.lbm_server_create.argtypes = [ctypes.POINTER(lbm_server_config), _VP,
+                                          ctypes.c_size_t, _VP, ctypes.POINTER(S)]
+        lib.lbm_server_create.restype = ctypes.c_int
+        lib.lbm_server_job_bytes.argtypes = [P, ctypes.c_int32]
+        lib.lbm_server_job_bytes.restype = ctypes.c_size_t
+        lib.lbm_server_submit.argtypes = [S, P, DP, ctypes.c_int64, DP, DP,
+                                          ctypes.POINTER(ctypes.c_int64)]
+        lib.lbm_server_submit.restype = ctypes.c_int
+        lib.lbm_server_advance.argtypes = [S, ctypes.POINTER(ctypes.c_int32)]
+        lib.lbm_server_advance.restype = ctypes.c_int
+        lib.lbm_server_poll.argtypes = [S, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+        lib.lbm_server_poll.restype = ctypes.c_int32
+        lib.lbm_server_get_stats.argtypes = [S, ctypes.POINTER(lbm_server_stats)]
+        lib.lbm_server_get_stats.restype = ctypes.c_int
+        lib.lbm_server_destroy.argtypes = [S]
+        lib.lbm_server_destroy.restype = None
         _lib = lib
     return _lib
 
@@ -121,7 +154,9 @@ EXPORTED = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_sync", "lbm_mome
             "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_batch_workspace_bytes",
             "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
             "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_destroy", "lbm_status_string",
-            "lbm_last_error", "lbm_destroy")
+            "lbm_last_error", "lbm_destroy", "lbm_server_create", "lbm_server_job_bytes",
+            "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
+            "lbm_server_get_stats", "lbm_server_destroy")
 
 
 def make_params(p: dict) -> lbm_params:
@@ -259,6 +294,57 @@ def lbm_batch_destroy(b):
     _load().lbm_batch_destroy(b)
 
 
+def lbm_server_create(max_resident, quantum, max_bypass, arena, stream):
+    srv = ctypes.c_void_p()
+    cfg = lbm_server_config(int(max_resident), int(quantum), int(max_bypass))
+    _check_b(_load().lbm_server_create(ctypes.byref(cfg), ctypes.c_void_p(arena.data_ptr()),
+                                       arena.numel() * arena.element_size(),
+                                       ctypes.c_void_p(stream.cuda_stream), ctypes.byref(srv)))
+    return srv.value
+
+
+def lbm_server_job_bytes(params, want_populations=False):
+    return _load().lbm_server_job_bytes(ctypes.byref(params), int(bool(want_populations)))
+
+
+def _host_ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lbm_server_submit(srv, params, rho0, nsteps, rho_out=None, f_out=None):
+    """rho0, rho_out, f_out: C-contiguous float64 NumPy arrays on the host."""
+    job = ctypes.c_int64()
+    _check_b(_load().lbm_server_submit(srv, ctypes.byref(params), _host_ptr(rho0), int(nsteps),
+                                       _host_ptr(rho_out), _host_ptr(f_out), ctypes.byref(job)))
+    return job.value
+
+
+def lbm_server_advance(srv):
+    n = ctypes.c_int32()
+    _check_b(_load().lbm_server_advance(srv, ctypes.byref(n)))
+    return n.value
+
+
+def lbm_server_poll(srv, max_jobs=1024):
+    ids = (ctypes.c_int64 * max_jobs)()
+    sts = (ctypes.c_int32 * max_jobs)()
+    n = _load().lbm_server_poll(srv, ids, sts, max_jobs)
+    return [(ids[k], sts[k]) for k in range(n)]
+
+
+def lbm_server_get_stats(srv):
+    out = lbm_server_stats()
+    _check_b(_load().lbm_server_get_stats(srv, ctypes.byref(out)))
+    return {name: getattr(out, name) for name, _ in out._fields_}
+
+
+def lbm_server_destroy(srv):
+    _load().lbm_server_destroy(srv)
+
+
 def lbm_last_error(h):
     return _load().lbm_last_error(h).decode()
 
@@ -374,6 +460,52 @@ class Batch:
     def close(self):
         if self.handle:
             lbm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching serving loop (include/lbm_server.h) over an arena of
+    `arena_bytes` device bytes on a stream of its own.  submit() takes host
+    NumPy arrays and keeps the output arrays alive until the job is polled."""
+
+    def __init__(self, arena_bytes, max_resident=256, quantum=64, max_bypass=8, device="cuda",
+                 stream=None):
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device)
+        self.handle = lbm_server_create(max_resident, quantum, max_bypass, self.arena,
+                                        self.stream)
+        self._outputs = {}
+
+    def submit(self, p: dict, rho0, nsteps, want_rho=True, want_populations=False):
+        params = make_params(p)
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+        assert rho0.shape == (params.ny, params.nx)
+        rho = np.empty((params.ny, params.nx)) if want_rho else None
+        f = np.empty((9, params.ny, params.nx)) if want_populations else None
+        job = lbm_server_submit(self.handle, params, rho0, nsteps, rho, f)
+        self._outputs[job] = (rho, f)
+        return job
+
+    def advance(self):
+        return lbm_server_advance(self.handle)
+
+    def poll(self):
+        """[(job id, status, rho or None, populations or None)] of jobs finished
+        since the last poll."""
+        return [(j, st) + self._outputs.pop(j) for j, st in lbm_server_poll(self.handle)]
+
+    def stats(self):
+        return lbm_server_get_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            lbm_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

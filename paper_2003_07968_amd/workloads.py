@@ -204,3 +204,36 @@ def batch_case(count=256, seed=6, storage="f32", side_range=(64, 512)):
         p["rho_ref"] = shift_reference(rho0, storage)
         out.append((p, rho0))
     return out
+
+
+def serve_case(count=64, seed=7, storage="f32", side_range=(64, 1024), steps_range=(2000, 50000)):
+    """A stream of independent jobs: square lattices with side = round(exp
+    U(ln 64, ln 1024)), steps ~ U{2000..50000}, a droplet (R0 = U[0.15, 0.35]
+    side) or a flat slab with equal odds, T_r ~ U[0.55, 0.95], sigma ~ U[1/8, 4],
+    tau = 1, eps = 1.73, W = 2, U(+-1e-3) noise.  Returns [(params, rho0, steps)]."""
+    rng = np.random.default_rng(seed)
+    lo, hi = side_range
+    out = []
+    for k in range(count):
+        side = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        nsteps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        tr = float(rng.uniform(0.55, 0.95))
+        sigma = float(rng.uniform(0.125, 4.0))
+        rg, rl = unit_cs_coexistence(tr)
+        if rng.random() < 0.5:
+            rho0 = droplet(side, side, float(rng.uniform(0.15, 0.35)) * side, rl, rg, 2.0)
+        else:
+            rho0 = slab(side, side, rl, rg, 2.0)
+        rho0 = rho0 + noise((side, side), seed * 100003 + k)
+        p = params(side, side, tr=tr, tau=1.0, sigma=sigma, storage=storage)
+        p["rho_ref"] = shift_reference(rho0, storage)
+        out.append((p, rho0, nsteps))
+    return out
+
+
+def poisson_arrivals(count, rate, seed=7):
+    """Arrival times (seconds from 0) of a Poisson process of the given rate:
+    cumulative sums of exponential gaps, the first job at 0."""
+    gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, size=count)
+    gaps[0] = 0.0
+    return np.cumsum(gaps)
