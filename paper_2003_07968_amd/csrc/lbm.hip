@@ -13,10 +13,13 @@
 // reductions are FP64 in every mode.
 //
 // Kernel design (one fused pass per step, HBM-bound):
-//   * populations are structure-of-arrays planes X_i[y][x] holding the
-//     post-collision values of the previous step; the pulled value is
-//     f_i(x) = X_i(x - c_i), so every plane row is read with unit stride
-//     (shifted by at most one element) and written with unit stride;
+//   * populations are arrays X_i[y][x] holding the post-collision values of
+//     the previous step; the pulled value is f_i(x) = X_i(x - c_i), so every
+//     row is read with unit stride (shifted by at most one element) and
+//     written with unit stride.  The nine rows X_0[y] .. X_8[y] of one y are
+//     stored one after another (row-interleaved), so that a row step reads
+//     and writes three neighbouring blocks of memory instead of nine regions
+//     a whole plane apart;
 //   * a workgroup of BX threads owns a strip of BX - 2 interior columns plus
 //     one halo column on each side, and walks a segment of rows.  At each row
 //     it loads the pulled populations of the row ahead, turns them into rho
@@ -25,10 +28,9 @@
 //     populations are prefetched one further row ahead.  Each population is
 //     read from HBM once per step, apart from the two halo columns per strip
 //     and the two halo rows per segment, which are re-read through L2;
-//   * workgroups are numbered so that consecutive tiles of the lattice (the
-//     strips of a row band) land on the same XCD and share its L2, and
-//     neighbouring segments walk in opposite directions, so both workgroups of
-//     a segment boundary touch its rows at about the same time.
+//   * neighbouring segments walk in opposite directions, so both workgroups
+//     of a segment boundary touch its rows at about the same time and the
+//     second reads them from L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,8 +80,8 @@ size_t elem_size(int storage)
 // Coefficients of one lattice, precomputed on the host.
 struct Coeffs {
     int nx, ny;
-    int pitch;      // row stride of a population plane, in elements (>= nx)
-    size_t plane;   // stride between population planes, in elements
+    int pitch;      // stride between rows y and y + 1 of one population, in elements
+    size_t plane;   // stride between populations i and i + 1 of one row, in elements
     double omega;   // 1/tau
     double guo;     // 1 - 1/(2 tau), Eq. GFSBGK
     double eos_b;   // b of Eq. CSEOS
@@ -233,33 +235,36 @@ __device__ __forceinline__ void velocity(const R d[kQ], R rho, R Fx, R Fy, R &ux
 //   f^eq_i - w_i rho_ref = w_i ((rho - rho_ref) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
 //   S_i                  = (1 - 1/(2 tau)) w_i (3 c.F + 9 (c.F)(c.u) - 3 u.F)
 //   d_i                 <- d_i + (f^eq_i - w_i rho_ref - d_i)/tau + S_i
-// Multiply-adds are written as explicit fma(); the file is compiled without
-// implicit contraction, so every inlined copy rounds the same way.
+// evaluated with the terms of f^eq and S gathered by powers of c_i (below),
+// about eight operations per direction.  Multiply-adds are written as
+// explicit fma(); the file is compiled without implicit contraction, so every
+// inlined copy rounds the same way.
 template <class R>
 __device__ __forceinline__ void collide(R d[kQ], R rho, R ux, R uy, R Fx, R Fy,
                                         const Phys<R> &P)
 {
+    // omega (f^eq_i - w_i rho_ref) + S_i = w_i [A + c_i.B + (c_i.u)(h c_i.u + m c_i.F)]
+    // with A = omega (rho (1 - 3/2 u.u) - rho_ref) - 3 g u.F, B = 3 (omega rho u + g F),
+    // h = 9/2 omega rho, m = 9 g (g = 1 - 1/(2 tau)); then d_i <- (1 - omega) d_i + w_i [..].
+    const R om = P.omega, g = P.guo;
+    const R orho = om * rho;
     const R usq = fma(ux, ux, uy * uy);
     const R uF = fma(ux, Fx, uy * Fy);
-    const R drho = rho - P.rho_ref;
-    const R q0 = R(-1.5) * usq;   // f^eq bracket without the c.u terms
-    const R sbase = R(-3) * uF;   // S bracket without the c.F terms
-    const R om = P.omega, g = P.guo;
+    const R A = fma(om, fma(rho, R(-1.5) * usq, rho - P.rho_ref), R(-3) * g * uF);
+    const R Bx = R(3) * fma(orho, ux, g * Fx), By = R(3) * fma(orho, uy, g * Fy);
+    const R h = R(4.5) * orho;
+    const R mx = R(9) * g * Fx, my = R(9) * g * Fy;
+    const R keep = R(1) - om;
     const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
-    const R gw0 = g * w0, gw1 = g * w1, gw2 = g * w2;
-    {
-        const R feq = w0 * fma(rho, q0, drho);
-        const R S = gw0 * sbase;
-        d[0] = fma(om, feq - d[0], d[0]) + S;
-    }
+    d[0] = fma(keep, d[0], w0 * A);
     const R cu[8] = {ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
-    const R cF[8] = {Fx, Fy, -Fx, -Fy, Fx + Fy, Fy - Fx, -Fx - Fy, Fx - Fy};
+    const R cm[8] = {mx, my, -mx, -my, mx + my, my - mx, -mx - my, mx - my};
+    const R cB[8] = {Bx, By, -Bx, -By, Bx + By, By - Bx, -Bx - By, Bx - By};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const R w = k < 4 ? w1 : w2, gw = k < 4 ? gw1 : gw2;
-        const R feq = w * fma(rho, fma(cu[k], fma(R(4.5), cu[k], R(3)), q0), drho);
-        const R S = gw * fma(cF[k], fma(R(9), cu[k], R(3)), sbase);
-        d[k + 1] = fma(om, feq - d[k + 1], d[k + 1]) + S;
+        const R w = k < 4 ? w1 : w2;
+        const R q = fma(cu[k], fma(h, cu[k], cm[k]), A + cB[k]);
+        d[k + 1] = fma(keep, d[k + 1], w * q);
     }
 }
 
@@ -731,18 +736,18 @@ struct Layout {
     size_t err, diag_out, partials, rho_snap, bufA, bufB, total, plane, pitch;
 };
 
-// Population storage.  Rows start on 128-byte boundaries (the pitch is nx
-// rounded up to 128 bytes), and consecutive planes are offset by 768 bytes
-// beyond a 256-byte multiple so that they do not all start on one
-// power-of-two boundary.  (Padding rows to an odd multiple of 128 bytes
-// measured slower on 2048-wide lattices.)
+// Population storage, row-interleaved: row y of population i starts at
+// element y * pitch + i * plane with plane = nx rounded up to 128 bytes and
+// pitch = 9 plane.  Every row starts on a 128-byte boundary.  (On 2048 x 2048
+// FP64 a 9-population stream in the kernel's walk order measured 6.3 TB/s in
+// this layout against 6.0 TB/s with whole planes one after another.)
 Layout layout_for(const lbm_params *p)
 {
     Layout L;
     const size_t n = (size_t)p->nx * p->ny;
     const size_t es = elem_size(p->storage);
-    L.pitch = round_up((size_t)p->nx, 128 / es);
-    L.plane = round_up(L.pitch * p->ny, kAlign / es) + 768 / es;
+    L.plane = round_up((size_t)p->nx, 128 / es);
+    L.pitch = kQ * L.plane;
     size_t off = 0;
     L.err = off;
     off += kAlign;
@@ -753,9 +758,9 @@ Layout layout_for(const lbm_params *p)
     L.rho_snap = off;
     off += round_up(n * sizeof(double), kAlign);
     L.bufA = off;
-    off += round_up(kQ * L.plane * es, kAlign);
+    off += round_up(L.pitch * p->ny * es, kAlign);
     L.bufB = off;
-    off += round_up(kQ * L.plane * es, kAlign);
+    off += round_up(L.pitch * p->ny * es, kAlign);
     L.total = off;
     return L;
 }
@@ -826,14 +831,15 @@ bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl,
     return true;
 }
 
-// Default launch shape: the workgroup width that wastes the fewest lanes on
-// ragged strips (ties to 256 threads), then row segments short enough for
-// about 64 waves per CU on 256 CUs (20 for FP16 storage), each segment at
-// least 5 rows.  Many short segments keep more rows of loads in flight per
-// CU (each segment starts with a burst of three row loads); their halo rows
-// come back mostly from cache.  Measured on 2048 x 2048: FP64 and FP32 are
-// fastest at (256 threads, 5 rows), FP16 at (256, 17), in sweeps over
-// 128..512 threads and 2..65 rows.
+// Default launch shape: 256-thread workgroups unless another width wastes
+// clearly fewer lanes on ragged strips (small lattices), then row segments
+// short enough for about 64 waves per CU on 256 CUs (20 for FP16 storage),
+// each segment at least 7 rows (FP64) or 5 rows (FP32, FP16).  Many short
+// segments keep more rows of loads in flight per CU (each segment starts with
+// a burst of three row loads); their halo rows come back mostly from cache.
+// Measured on 2048 x 2048 in sweeps over 128..512 threads and 3..25 rows:
+// FP64 is fastest at (256 threads, 7 rows), FP32 at (256, 5), FP16 at
+// (256, 17).
 void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
 {
     int best = 256;
@@ -843,7 +849,7 @@ void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
         Tiles tl;
         if (!make_tiles(nx, ny, bx, 1 << 30, align, &tl)) continue;
         const double eff = (double)nx / ((double)tl.nstrips * bx);
-        const double score = eff - (bx > 256 ? 0.02 : 0.0) + (bx == 256 ? 0.02 : 0.0);
+        const double score = eff - (bx > 256 ? 0.1 : 0.0) + (bx == 256 ? 0.1 : 0.0);
         if (score > best_score + 1e-12) {
             best_score = score;
             best = bx;
@@ -855,7 +861,7 @@ void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
     int nseg = (int)std::ceil(target_waves / ((double)tb.nstrips * (best / 64)));
     nseg = std::max(1, std::min(nseg, ny));
     int rows = (ny + nseg - 1) / nseg;
-    rows = std::max(rows, std::min(5, ny));
+    rows = std::max(rows, std::min(storage == LBM_STORE_F64 ? 7 : 5, ny));
     while ((long long)tb.nstrips * ((ny + rows - 1) / rows) > kMaxTiles)
         ++rows;
     *bx_out = best;
