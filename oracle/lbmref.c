@@ -136,6 +136,106 @@ void lbmref_guo_source(double tau, double ux, double uy, double Fx, double Fy, d
     }
 }
 
+void lbmref_guo_term(double ux, double uy, double Fx, double Fy, double s[9])
+{
+    double u[2] = {ux, uy};
+    double F[2] = {Fx, Fy};
+    for (int i = 0; i < 9; ++i) {
+        double lin = 0.0, quad = 0.0;
+        for (int a = 0; a < 2; ++a)
+            lin += c_comp(i, a) * F[a] / CS2;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                quad += (c_comp(i, a) * c_comp(i, b) - CS2 * kdelta(a, b)) * F[a] * u[b] /
+                        (CS2 * CS2);
+        s[i] = W[i] * (lin + quad);
+    }
+}
+
+/* Gram-Schmidt moment matrix of Appendix A (Eq. MatrixMRT); rows are the
+ * moments rho, e, zeta, j_x, q_x, j_y, q_y, p_xx, p_xy. */
+static const double MRT_M[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1},
+};
+
+void lbmref_mrt_matrix(double M[81])
+{
+    for (int k = 0; k < 9; ++k)
+        for (int i = 0; i < 9; ++i)
+            M[9 * k + i] = MRT_M[k][i];
+}
+
+/* Inverse of a 9 x 9 matrix by Gauss-Jordan elimination with partial
+ * pivoting; returns -1 if it is singular. */
+static int invert9(const double A[81], double Ainv[81])
+{
+    double a[9][18];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 18; ++c)
+            a[r][c] = c < 9 ? A[9 * r + c] : (c - 9 == r ? 1.0 : 0.0);
+    for (int col = 0; col < 9; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 9; ++r)
+            if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+        if (a[piv][col] == 0.0) return -1;
+        if (piv != col)
+            for (int c = 0; c < 18; ++c) {
+                double t = a[col][c];
+                a[col][c] = a[piv][c];
+                a[piv][c] = t;
+            }
+        double d = a[col][col];
+        for (int c = 0; c < 18; ++c)
+            a[col][c] /= d;
+        for (int r = 0; r < 9; ++r)
+            if (r != col) {
+                double m = a[r][col];
+                for (int c = 0; c < 18; ++c)
+                    a[r][c] -= m * a[col][c];
+            }
+    }
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c)
+            Ainv[9 * r + c] = a[r][9 + c];
+    return 0;
+}
+
+static int check_params(const lbmref_params *p);
+
+/* Relaxation matrix of Eq. RelaxationMatrix:
+ * Lambda = diag(1/tau_rho, 1/tau_e, 1/tau_zeta, 1/tau_j, 1/tau_q, 1/tau_j,
+ *               1/tau_q, 1/tau_nu, 1/tau_nu), tau_nu = tau. */
+int lbmref_mrt_operators(const lbmref_params *p, double K[81], double C[81])
+{
+    int st = check_params(p);
+    if (st) return st;
+    double M[81], Minv[81];
+    lbmref_mrt_matrix(M);
+    if (invert9(M, Minv)) return LBMREF_ERR_INVALID_ARG;
+    double lam[9] = {1.0 / p->tau_rho, 1.0 / p->tau_e, 1.0 / p->tau_zeta,
+                     1.0 / p->tau_j,   1.0 / p->tau_q, 1.0 / p->tau_j,
+                     1.0 / p->tau_q,   1.0 / p->tau,   1.0 / p->tau};
+    for (int i = 0; i < 9; ++i)
+        for (int j = 0; j < 9; ++j) {
+            double k = 0.0, c = 0.0;
+            for (int m = 0; m < 9; ++m) {
+                k += Minv[9 * i + m] * lam[m] * M[9 * m + j];
+                c += Minv[9 * i + m] * (1.0 - lam[m] / 2.0) * M[9 * m + j];
+            }
+            K[9 * i + j] = k;
+            C[9 * i + j] = c;
+        }
+    return LBMREF_OK;
+}
+
 /* Moments of w_i psi(x + c_i), Sec. III.B (Eqs. ZOMED, FOMED, SOMED). */
 static void moments_at(int32_t nx, int32_t ny, const double *psi, int x, int y, double *M0,
                        double M1[2], double M2[2][2])
@@ -252,6 +352,12 @@ static int check_params(const lbmref_params *p)
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return LBMREF_ERR_INVALID_ARG;
     if (!(p->G != 0.0) || !isfinite(p->G)) return LBMREF_ERR_INVALID_ARG;
     if (p->storage < 0 || p->storage > 2 || !isfinite(p->rho_ref)) return LBMREF_ERR_INVALID_ARG;
+    if (p->collision != 0 && p->collision != 1) return LBMREF_ERR_INVALID_ARG;
+    if (p->collision == 1) {
+        const double taus[5] = {p->tau_rho, p->tau_e, p->tau_zeta, p->tau_j, p->tau_q};
+        for (int k = 0; k < 5; ++k)
+            if (!(taus[k] > 0.5) || !isfinite(taus[k])) return LBMREF_ERR_INVALID_ARG;
+    }
     return LBMREF_OK;
 }
 
@@ -359,7 +465,11 @@ int lbmref_moments(const lbmref_params *p, const double *f, double *rho, double 
  * and the Guo source (Eqs. GFS, GFSBGK):
  *   f*_i(x) = f_i(x) - (f_i(x) - f_i^eq(x))/tau + S_i(x)     (collision)
  *   f_i(x + c_i, t + 1) = f*_i(x)                          (streaming)
- * with f^eq and S evaluated at the velocity of Eq. FMD. */
+ * or, with collision = 1, the MRT operator (Eq. MRTCO) and the MRT Guo
+ * factor (Eq. GFSMRT):
+ *   f*_i(x) = f_i - sum_j K_ij (f_j - f_j^eq) + sum_j C_ij s_j
+ * with K = M^-1 Lambda M, C = M^-1 (I - Lambda/2) M and s the bracket of
+ * Eq. GFS; f^eq and s evaluated at the velocity of Eq. FMD. */
 int lbmref_step(const lbmref_params *p, double *f, int64_t nsteps, lbmref_fault *fault)
 {
     int st = check_params(p);
@@ -376,6 +486,11 @@ int lbmref_step(const lbmref_params *p, double *f, int64_t nsteps, lbmref_fault 
     if (!rho || !psi || !Fx || !Fy || !ux || !uy || !fpost) {
         st = LBMREF_ERR_INVALID_ARG;
         goto done;
+    }
+    double K[81], C[81];
+    if (p->collision == 1) {
+        st = lbmref_mrt_operators(p, K, C);
+        if (st) goto done;
     }
     for (int64_t t = 0; t < nsteps; ++t) {
         int64_t bad = -1;
@@ -395,6 +510,21 @@ int lbmref_step(const lbmref_params *p, double *f, int64_t nsteps, lbmref_fault 
                 size_t k = (size_t)y * p->nx + x;
                 double feq[9], S[9];
                 lbmref_equilibrium(rho[k], ux[k], uy[k], feq);
+                if (p->collision == 1) {
+                    double s[9], neq[9];
+                    lbmref_guo_term(ux[k], uy[k], Fx[k], Fy[k], s);
+                    for (int j = 0; j < 9; ++j)
+                        neq[j] = f[(size_t)j * n + k] - feq[j];
+                    for (int i = 0; i < 9; ++i) {
+                        double relax = 0.0, src = 0.0;
+                        for (int j = 0; j < 9; ++j) {
+                            relax += K[9 * i + j] * neq[j];
+                            src += C[9 * i + j] * s[j];
+                        }
+                        fpost[(size_t)i * n + k] = f[(size_t)i * n + k] - relax + src;
+                    }
+                    continue;
+                }
                 lbmref_guo_source(p->tau, ux[k], uy[k], Fx[k], Fy[k], S);
                 for (int i = 0; i < 9; ++i) {
                     double fi = f[(size_t)i * n + k];

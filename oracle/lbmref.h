@@ -48,6 +48,13 @@ typedef struct {
                              binary32 (1) or binary16 (2) after every step and
                              at initialisation (reduced-precision storage)    */
     double rho_ref;       /* reference density of the stored deviations       */
+    int32_t collision;    /* 0: BGK (Eq. BGKCO) with the Guo factor of
+                             Eq. GFSBGK; 1: MRT (Eq. MRTCO) with the Guo
+                             factor of Eq. GFSMRT, moment matrix of
+                             Eq. MatrixMRT (Appendix A)                        */
+    double tau_rho, tau_e, tau_zeta, tau_j, tau_q; /* MRT relaxation times of
+                             Eq. RelaxationMatrix; the stress rows relax with
+                             tau_nu = tau.  Ignored for BGK.                   */
 } lbmref_params;
 
 /* Diagnostic record of the first domain failure (cell = y*nx + x). */
@@ -63,6 +70,16 @@ int lbmref_psi(const lbmref_params *p, double rho, double *psi);          /* Eq.
 void lbmref_equilibrium(double rho, double ux, double uy, double feq[9]); /* Eq. SEDF  */
 void lbmref_guo_source(double tau, double ux, double uy, double Fx, double Fy,
                        double S[9]);                                      /* Eqs. GFS, GFSBGK */
+/* The bracket of Eq. GFS without C_ij:
+ * s_j = w_j [ c_ja F_a / cs^2 + (c_ja c_jb - cs^2 d_ab) F_a u_b / cs^4 ]. */
+void lbmref_guo_term(double ux, double uy, double Fx, double Fy, double s[9]);
+/* The moment matrix M of Eq. MatrixMRT, row-major (M[9 k + i] = M_ki). */
+void lbmref_mrt_matrix(double M[81]);
+/* The MRT collision matrices of the parameters: K = M^-1 Lambda M
+ * (Eq. MRTCO) and C = M^-1 (I - Lambda/2) M (Eq. GFSMRT), row-major, with
+ * M^-1 from Gauss-Jordan elimination.  Returns LBMREF_ERR_INVALID_ARG for
+ * invalid parameters. */
+int lbmref_mrt_operators(const lbmref_params *p, double K[81], double C[81]);
 
 /* Field operations over a periodic psi field [ny][nx]. */
 void lbmref_psi_moments(int32_t nx, int32_t ny, const double *psi, double *M0,

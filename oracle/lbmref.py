@@ -27,6 +27,9 @@ class Params(ctypes.Structure):
         ("eos_c", ctypes.c_double), ("eos_k", ctypes.c_double), ("T", ctypes.c_double),
         ("force_on", ctypes.c_int32), ("m2_trace_alt", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("rho_ref", ctypes.c_double),
+        ("collision", ctypes.c_int32),
+        ("tau_rho", ctypes.c_double), ("tau_e", ctypes.c_double), ("tau_zeta", ctypes.c_double),
+        ("tau_j", ctypes.c_double), ("tau_q", ctypes.c_double),
     ]
 
 
@@ -62,6 +65,11 @@ def _load():
         lib.lbmref_equilibrium.restype = None
         lib.lbmref_guo_source.argtypes = [ctypes.c_double] * 5 + [_DP]
         lib.lbmref_guo_source.restype = None
+        lib.lbmref_guo_term.argtypes = [ctypes.c_double] * 4 + [_DP]
+        lib.lbmref_guo_term.restype = None
+        lib.lbmref_mrt_matrix.argtypes = [_DP]
+        lib.lbmref_mrt_matrix.restype = None
+        lib.lbmref_mrt_operators.argtypes = [P, _DP, _DP]
         lib.lbmref_psi_moments.argtypes = [ctypes.c_int32, ctypes.c_int32] + [_DP] * 7
         lib.lbmref_psi_moments.restype = None
         lib.lbmref_force.argtypes = [P, _DP, _DP, _DP]
@@ -88,12 +96,19 @@ def _ptr(a):
 STORE_F64, STORE_F32, STORE_F16 = 0, 1, 2
 
 
+COLL_BGK, COLL_MRT = 0, 1
+
+
 def make_params(nx, ny, tau=1.0, G=-1.0, epsilon=1.73, sigma=1.0, eos=(1.0, 1.0, 1.0, 1.0),
-                T=0.0, force_on=True, m2_trace_alt=False, storage=0, rho_ref=0.0) -> Params:
+                T=0.0, force_on=True, m2_trace_alt=False, storage=0, rho_ref=0.0,
+                collision=COLL_BGK, mrt=(1.0, 1.0, 1.0, 1.0, 1.0)) -> Params:
+    """mrt = (tau_rho, tau_e, tau_zeta, tau_j, tau_q) of Eq. RelaxationMatrix; the
+    stress rows relax with tau."""
     a, b, c, k = eos
     return Params(int(nx), int(ny), float(tau), float(G), float(epsilon), float(sigma),
                   float(a), float(b), float(c), float(k), float(T), int(bool(force_on)),
-                  int(bool(m2_trace_alt)), int(storage), float(rho_ref))
+                  int(bool(m2_trace_alt)), int(storage), float(rho_ref), int(collision),
+                  *[float(v) for v in mrt])
 
 
 def quantize(storage, x):
@@ -127,6 +142,28 @@ def guo_source(tau, ux, uy, Fx, Fy):
     out = np.zeros(9)
     _load().lbmref_guo_source(float(tau), float(ux), float(uy), float(Fx), float(Fy), _ptr(out))
     return out
+
+
+def guo_term(ux, uy, Fx, Fy):
+    out = np.zeros(9)
+    _load().lbmref_guo_term(float(ux), float(uy), float(Fx), float(Fy), _ptr(out))
+    return out
+
+
+def mrt_matrix():
+    out = np.zeros(81)
+    _load().lbmref_mrt_matrix(_ptr(out))
+    return out.reshape(9, 9)
+
+
+def mrt_operators(p: Params):
+    """(K, C) = (M^-1 Lambda M, M^-1 (I - Lambda/2) M) of the parameters."""
+    K = np.zeros(81)
+    C = np.zeros(81)
+    st = _load().lbmref_mrt_operators(ctypes.byref(p), _ptr(K), _ptr(C))
+    if st != OK:
+        raise OracleError(st)
+    return K.reshape(9, 9), C.reshape(9, 9)
 
 
 def psi_moments(psi_field):

@@ -65,11 +65,17 @@ def unit_cs_coexistence(tr: float):
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 
 
+COLLISION = {"bgk": 0, "mrt": 1}
+
+
 def params(nx, ny, tr=0.8, tau=1.0, G=-1.0, epsilon=1.73, sigma=1.0, eos="unit",
-           force_on=True, m2_trace_alt=False, storage="f64", rho_ref=0.0):
+           force_on=True, m2_trace_alt=False, storage="f64", rho_ref=0.0, collision="bgk",
+           mrt=(1.0, 1.0, 1.0, 1.0, 1.0)):
     """A parameter dictionary in the field names of the library's parameter block.
     storage is "f64", "f32" or "f16" (the last two store deviations from
-    w_i rho_ref)."""
+    w_i rho_ref).  collision is "bgk" or "mrt"; mrt holds the MRT relaxation
+    times (tau_rho, tau_e, tau_zeta, tau_j, tau_q), the stress rows relaxing
+    with tau."""
     if eos == "unit":
         p = dict(UNIT_CS)
         T = tr * UNIT_CS_TC
@@ -80,7 +86,9 @@ def params(nx, ny, tr=0.8, tau=1.0, G=-1.0, epsilon=1.73, sigma=1.0, eos="unit",
         raise ValueError(eos)
     p.update(nx=int(nx), ny=int(ny), tau=float(tau), G=float(G), epsilon=float(epsilon),
              sigma=float(sigma), T=float(T), force_on=bool(force_on),
-             m2_trace_alt=bool(m2_trace_alt), storage=STORAGE[storage], rho_ref=float(rho_ref))
+             m2_trace_alt=bool(m2_trace_alt), storage=STORAGE[storage], rho_ref=float(rho_ref),
+             collision=COLLISION[collision])
+    p.update(zip(("tau_rho", "tau_e", "tau_zeta", "tau_j", "tau_q"), (float(v) for v in mrt)))
     return p
 
 
