@@ -17,6 +17,9 @@ the same workload.
 --storage f32 / f16 runs the same workload with populations stored as FP32 /
 FP16 deviations from w_i rho_ref (FP32 arithmetic; 72 / 36 bytes per cell).
 
+--collision mrt runs it with the MRT collision (moment matrix of Appendix A,
+Lambda = diag(1, ..., 1, 1/tau, 1/tau) as in the paper's oscillation runs).
+
 --workload batch measures the batched form instead: 256 uneven droplet
 lattices in FP32-shifted storage (or --storage f16), one launch per step,
 against the same lattices stepped one by one in FP64.
@@ -26,7 +29,8 @@ server (FP32- and FP16-shifted) and reports p50/p99 time-to-result beside the
 same jobs run one after another on the plain FP64 path.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--storage f64|f32|f16] [--workload slab|batch|serve] [--jobs J]
+                       [--storage f64|f32|f16] [--collision bgk|mrt]
+                       [--workload slab|batch|serve] [--jobs J]
        python bench.py --copy-calibration   (plain copy kernel for PMC scaling)
 """
 import argparse
@@ -325,6 +329,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--storage", choices=sorted(BYTES_PER_CELL), default="f64")
+    ap.add_argument("--collision", choices=("bgk", "mrt"), default="bgk")
     ap.add_argument("--workload", choices=("slab", "batch", "serve"), default="slab")
     ap.add_argument("--jobs", type=int, default=64, help="jobs in the serving stream")
     args = ap.parse_args()
@@ -356,6 +361,7 @@ def main():
         p, rho0 = W.slab_case(n=N, tr=tr)
         p["storage"] = W.STORAGE[args.storage]
         p["rho_ref"] = W.shift_reference(rho0, args.storage)
+        p["collision"] = W.COLLISION[args.collision]
         lats.append(lbm.Lattice(p, rho0))
     launch = lats[0].launch()
     err(f"lattices ready, launch shape {launch}")
@@ -391,7 +397,7 @@ def main():
     launch_ms = gpu_ms / (args.steps * len(lats))
     bpc = BYTES_PER_CELL[args.storage]
     achieved = bpc * N * N / (launch_ms / 1e3) / 1e9
-    traffic = measured_traffic(args.storage)
+    traffic = measured_traffic(args.storage) if args.collision == "bgk" else None
 
     out = {
         "metric": METRIC,
@@ -411,7 +417,7 @@ def main():
             "workload": "D2Q9 2048x2048 periodic flat slab, T_r in {0.6,0.7,0.8,0.9} "
                         "(four lattices), tau=1, Carnahan-Starling a=1 b=4 R=1, G=-1, "
                         "eps=1.73, sigma=1, W=2, seeded +-1e-3 noise",
-            "storage": args.storage,
+            "storage": args.storage, "collision": args.collision,
             "lattices": len(lats), "nx": N, "ny": N,
             "bytes_per_cell_update": bpc,
             "launch_block_x_seg_rows_workgroups": list(launch),
@@ -423,7 +429,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"sweep_kernel (step mode, {args.storage} storage)",
+            "kernel": f"sweep_kernel (step mode, {args.storage} storage, {args.collision})",
             "kernel_avg_ms": round(launch_ms, 5),
         },
     }

@@ -20,6 +20,10 @@
  *   7. BGK collision with the Guo source                (Eqs. BGKCO, GFS, GFSBGK)
  *      f*_i = f_i - (f_i - f_i^eq)/tau + (1 - 1/(2 tau)) w_i [c_i.F/cs^2
  *             + (c_ia c_ib - cs^2 d_ab) F_a u_b / cs^4],  f^eq of Eq. SEDF
+ *      or the MRT collision with the Guo source      (Eqs. MRTCO, GFS, GFSMRT)
+ *      f* = f - M^-1 Lambda M (f - f^eq) + M^-1 (I - Lambda/2) M s,
+ *      with the Gram-Schmidt moment matrix M of Eq. MatrixMRT (Appendix A),
+ *      Lambda of Eq. RelaxationMatrix and s the bracket of Eq. GFS
  *
  * with the D2Q9 velocities and weights of Sec. II.A (Eq. VelocitySet),
  * cs^2 = 1/3, in FP64 (or, with reduced-precision storage, FP32; see
@@ -67,6 +71,12 @@ typedef enum {
 } lbm_status;
 
 typedef enum {
+    LBM_COLL_BGK = 0,          /* single relaxation time, Eq. BGKCO, Guo factor Eq. GFSBGK  */
+    LBM_COLL_MRT = 1           /* multiple relaxation times, Eq. MRTCO, Guo factor
+                                  Eq. GFSMRT, moment matrix of Eq. MatrixMRT               */
+} lbm_collision;
+
+typedef enum {
     LBM_STORE_F64 = 0,         /* populations stored in FP64, FP64 arithmetic           */
     LBM_STORE_F32_SHIFTED = 1, /* stored as FP32 deviations f_i - w_i rho_ref, FP32
                                   arithmetic (72 bytes per cell update)                */
@@ -94,6 +104,17 @@ typedef struct {
                          them.  Diagnostics sums stay FP64.                      */
     double rho_ref;   /* reference density of the shifted modes (normally the mean
                          initial density); ignored for LBM_STORE_F64              */
+    int32_t collision; /* lbm_collision                                            */
+    double tau_rho, tau_e, tau_zeta, tau_j, tau_q;
+                      /* MRT relaxation times of Eq. RelaxationMatrix, each > 0.5:
+                         Lambda = diag(1/tau_rho, 1/tau_e, 1/tau_zeta, 1/tau_j,
+                         1/tau_q, 1/tau_j, 1/tau_q, 1/tau, 1/tau) on the moments
+                         (rho, e, zeta, j_x, q_x, j_y, q_y, p_xx, p_xy); the stress
+                         rows relax with tau, which sets the viscosity
+                         cs^2 (tau - 1/2).  The mass and momentum rows are
+                         conserved by the collision with the Guo source, so
+                         tau_rho and tau_j do not change the result.  Ignored
+                         for LBM_COLL_BGK.                                       */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -175,8 +196,8 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3]);
 /* ---- Batches: many lattices advanced together by one kernel launch per step ----
  *
  * A batch holds up to `capacity` handles created by lbm_init on the same HIP
- * stream, all with the same storage mode and force_on, any sizes and any other
- * parameters.  lbm_batch_step launches one kernel per time step covering every
+ * stream, all with the same storage mode, force_on and collision, any sizes
+ * and any other parameters.  lbm_batch_step launches one kernel per time step covering every
  * tile of every lattice (a workgroup finds its lattice in a device table), and
  * replays a captured HIP graph of eight steps for every full eight steps of a
  * call (not on the legacy null stream, which cannot be captured: there each
@@ -200,7 +221,7 @@ lbm_status lbm_batch_create(int32_t capacity, void *d_workspace, size_t workspac
 
 /* Add or remove a handle (the handle stays owned by the caller).  Adding fails
  * with LBM_ERR_INVALID_ARG if the batch is full, the handle is already in it,
- * or its storage mode, force_on or stream differ from the batch's. */
+ * or its storage mode, force_on, collision or stream differ from the batch's. */
 lbm_status lbm_batch_add(lbm_batch *b, lbm_handle *h);
 lbm_status lbm_batch_remove(lbm_batch *b, lbm_handle *h);
 int32_t lbm_batch_size(const lbm_batch *b);

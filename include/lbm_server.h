@@ -6,8 +6,9 @@
  * scheduling round (lbm_server_advance) admits waiting jobs while their
  * device-memory footprint fits in the server's arena and a resident slot is
  * free, advances every resident lattice by the same number of steps with one
- * batched launch per step (lbm_batch_step; one batch per storage mode and
- * force switch), and retires the jobs that have reached their step count,
+ * batched launch per step (lbm_batch_step; one batch per storage mode, force
+ * switch and collision operator, each holding a table for max_resident
+ * lattices in the arena), and retires the jobs that have reached their step count,
  * copying their results to host memory.  A job's result is bitwise the one it
  * gives when run alone with lbm_init / lbm_step, whatever else was resident.
  *

@@ -5,7 +5,9 @@
 // streaming (Eq. TLBE), density (Eq. FD), Carnahan-Starling pressure
 // (Eq. CSEOS), pseudopotential (Eq. DED), psi moments (Eqs. FOMED, SOMED), the
 // proposed force (Eq. IFT), velocity (Eq. FMD) and the Guo-forced BGK
-// collision (Eqs. BGKCO, SEDF, GFS, GFSBGK).
+// collision (Eqs. BGKCO, SEDF, GFS, GFSBGK), or the multiple-relaxation-time
+// collision with the Guo source in moment space (Eqs. MRTCO, GFSMRT, the
+// Gram-Schmidt moment matrix of Eq. MatrixMRT).
 //
 // Storage modes: FP64 populations with FP64 arithmetic, or populations kept
 // as deviations d_i = f_i - w_i rho_ref in FP32 or FP16 with FP32 arithmetic
@@ -94,6 +96,8 @@ struct Coeffs {
     // = 9G (1.5 eps - sigma + 1); cB = (sigma - 1) cs^2 G / cs^6 = 9G (sigma - 1).
     double cSC, cA, cB;
     double rho_ref; // populations are stored as f_i - w_i rho_ref (0 for FP64)
+    double s_e, s_z, s_q; // MRT rates 1/tau_e, 1/tau_zeta, 1/tau_q (the stress rows use omega)
+    int coll;       // lbm_collision
     int force_on;
     int trace_alt;
     int storage;
@@ -102,12 +106,12 @@ struct Coeffs {
 // The coefficients in the arithmetic type of a storage mode.
 template <class R>
 struct Phys {
-    R omega, guo, eos_b, kcT, ka, invG, cSC, cA, cB, rho_ref;
+    R omega, guo, eos_b, kcT, ka, invG, cSC, cA, cB, rho_ref, s_e, s_z, s_q;
     int trace_alt;
     __device__ explicit Phys(const Coeffs &c)
         : omega((R)c.omega), guo((R)c.guo), eos_b((R)c.eos_b), kcT((R)c.kcT), ka((R)c.ka),
           invG((R)c.invG), cSC((R)c.cSC), cA((R)c.cA), cB((R)c.cB), rho_ref((R)c.rho_ref),
-          trace_alt(c.trace_alt)
+          s_e((R)c.s_e), s_z((R)c.s_z), s_q((R)c.s_q), trace_alt(c.trace_alt)
     {
     }
 };
@@ -268,6 +272,66 @@ __device__ __forceinline__ void collide(R d[kQ], R rho, R ux, R uy, R Fx, R Fy,
     }
 }
 
+// Multiple-relaxation-time collision with the Guo source (Eqs. MRTCO, GFSMRT)
+// on the deviations d_i = f_i - w_i rho_ref, in place, in the moment space of
+// the Gram-Schmidt matrix M of Eq. MatrixMRT (rows rho, e, zeta, j_x, q_x,
+// j_y, q_y, p_xx, p_xy):
+//   m* = m - Lambda (m - m^eq) + (I - Lambda/2) S_bar,   d* = M^-1 m*
+// with m^eq and S_bar = M s of Appendix A.  For the deviations, M (w rho_ref)
+// = rho_ref (1, -2, 1, 0, ..., 0) is taken out of the rho, e and zeta rows.
+// The rho row is unchanged (m = m^eq, no source) and the momentum rows give
+// m_j + F for every rate (m_j - m_j^eq = -F/2), so tau_rho and tau_j drop out.
+// The rows of M are orthogonal, so M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12,
+// 1/6, 1/12, 1/4, 1/4).
+template <class R>
+__device__ __forceinline__ void collide_mrt(R d[kQ], R rho, R ux, R uy, R Fx, R Fy,
+                                            const Phys<R> &P)
+{
+    const R dr = (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8];
+    const R ax = (d[1] + d[2]) + (d[3] + d[4]);             // axis directions
+    const R dg = (d[5] + d[6]) + (d[7] + d[8]);             // diagonal directions
+    const R e = fma(R(-4), d[0], fma(R(2), dg, -ax));
+    const R z = fma(R(4), d[0], fma(R(-2), ax, dg));
+    const R jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]);
+    const R jy = ((d[2] - d[4]) + (d[5] + d[6])) - (d[7] + d[8]);
+    const R qx = fma(R(-2), d[1] - d[3], (d[5] - d[7]) + (d[8] - d[6]));
+    const R qy = fma(R(-2), d[2] - d[4], (d[5] - d[7]) + (d[6] - d[8]));
+    const R pxx = (d[1] + d[3]) - (d[2] + d[4]);
+    const R pxy = (d[5] + d[7]) - (d[6] + d[8]);
+
+    const R usq = fma(ux, ux, uy * uy);
+    const R uF6 = R(6) * fma(ux, Fx, uy * Fy);
+    const R rusq3 = R(3) * rho * usq;
+    const R se = P.s_e, sz = P.s_z, sq = P.s_q, sn = P.omega;
+    const R es = fma(R(1) - se, e, fma(se, fma(R(-2), dr, rusq3), (R(1) - R(0.5) * se) * uF6));
+    const R zs = fma(R(1) - sz, z, fma(sz, dr - rusq3, -(R(1) - R(0.5) * sz) * uF6));
+    const R jxs = jx + Fx, jys = jy + Fy;
+    const R gq = R(1) - R(0.5) * sq;
+    const R qxs = fma(R(1) - sq, qx, -fma(sq * rho, ux, gq * Fx));
+    const R qys = fma(R(1) - sq, qy, -fma(sq * rho, uy, gq * Fy));
+    const R gn = R(1) - R(0.5) * sn;
+    const R pxxs = fma(R(1) - sn, pxx,
+                       fma(sn * rho, fma(ux, ux, -uy * uy), gn * R(2) * fma(ux, Fx, -uy * Fy)));
+    const R pxys = fma(R(1) - sn, pxy, fma(sn * rho, ux * uy, gn * fma(ux, Fy, uy * Fx)));
+
+    const R r9 = dr * R(1.0 / 9.0);
+    const R A1 = fma(es, R(-1.0 / 36.0), fma(zs, R(-1.0 / 18.0), r9));
+    const R A2 = fma(es, R(1.0 / 18.0), fma(zs, R(1.0 / 36.0), r9));
+    const R X1 = (jxs - qxs) * R(1.0 / 6.0), Y1 = (jys - qys) * R(1.0 / 6.0);
+    const R X2 = fma(jxs, R(1.0 / 6.0), qxs * R(1.0 / 12.0));
+    const R Y2 = fma(jys, R(1.0 / 6.0), qys * R(1.0 / 12.0));
+    const R Pp = pxxs * R(0.25), Qp = pxys * R(0.25);
+    d[0] = fma(zs - es, R(1.0 / 9.0), r9);
+    d[1] = (A1 + X1) + Pp;
+    d[2] = (A1 + Y1) - Pp;
+    d[3] = (A1 - X1) + Pp;
+    d[4] = (A1 - Y1) - Pp;
+    d[5] = (A2 + X2) + (Y2 + Qp);
+    d[6] = (A2 - X2) + (Y2 - Qp);
+    d[7] = (A2 - X2) - (Y2 - Qp);
+    d[8] = (A2 + X2) - (Y2 + Qp);
+}
+
 __device__ __forceinline__ double weight(int i)
 {
     return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
@@ -366,7 +430,7 @@ __device__ __forceinline__ void unroll(F &&f, std::integer_sequence<int, J...>)
 // around the loads the compiler's wait counters stay exact, so a prefetch
 // really stays in flight while the current row is computed.  Domain
 // failures are folded into a per-lane minimum key and published once.
-template <int BX, int MODE, int DIR, int PF, int FORCE, int ST>
+template <int BX, int MODE, int DIR, int PF, int FORCE, int ST, int COLL>
 __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ src,
                                      typename Store<ST>::E *__restrict__ dst, const Coeffs &c,
                                      long long t, const Fields &fo, double *__restrict__ rho_snap,
@@ -443,7 +507,10 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
         velocity<R>(f[cur], C.rho, Fx, Fy, ux, uy);
         const size_t row = (size_t)y * c.nx;
         if (MODE == kStep) {
-            collide<R>(f[cur], C.rho, ux, uy, Fx, Fy, P);
+            if constexpr (COLL == LBM_COLL_MRT)
+                collide_mrt<R>(f[cur], C.rho, ux, uy, Fx, Fy, P);
+            else
+                collide<R>(f[cur], C.rho, ux, uy, Fx, Fy, P);
             if (interior) {
                 const size_t prow = (size_t)y * c.pitch;
 #pragma unroll
@@ -487,7 +554,7 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
 }
 
 // One tile of a sweep: strip `strip` of row band `seg` of one lattice.
-template <int BX, int MODE, int PF, int FORCE, int ST>
+template <int BX, int MODE, int PF, int FORCE, int ST, int COLL>
 __device__ __forceinline__ void sweep_tile(const void *__restrict__ src_v, void *__restrict__ dst_v,
                                            const Coeffs &c, const Tiles &tl, int tile,
                                            long long t, unsigned long long *__restrict__ err,
@@ -519,10 +586,10 @@ __device__ __forceinline__ void sweep_tile(const void *__restrict__ src_v, void 
     double acc[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     unsigned long long bad = ~0ull;
     if (seg & 1)
-        walk<BX, MODE, -1, PF, FORCE, ST>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
+        walk<BX, MODE, -1, PF, FORCE, ST, COLL>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
                                           interior, lds, acc, bad);
     else
-        walk<BX, MODE, +1, PF, FORCE, ST>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
+        walk<BX, MODE, +1, PF, FORCE, ST, COLL>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
                                           interior, lds, acc, bad);
     if (bad != ~0ull) atomicMin(err, bad);
 
@@ -541,10 +608,21 @@ __device__ __forceinline__ void sweep_tile(const void *__restrict__ src_v, void 
     }
 }
 
-// One sweep over one lattice: tiles are numbered row band by row band;
-// workgroups are dealt to the 8 XCDs round-robin, so the strips of one band
-// run side by side.
-template <int BX, int MODE, int PF, int FORCE, int ST>
+// Workgroups are dealt to the 8 XCDs of the chip round-robin (workgroup b
+// runs on XCD b mod 8), and each XCD has an L2 of its own.  Tile of workgroup
+// b among n tiles numbered row band by row band: XCD k takes the contiguous
+// run of tiles [start(k), start(k + 1)), so the workgroups that share a
+// segment's halo rows or a strip's halo columns run on the same XCD, at about
+// the same time, and re-read them from its L2.  A bijection of [0, n) for
+// every n.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int xcd = b & 7, j = b >> 3, base = n >> 3, rem = n & 7;
+    return xcd * base + min(xcd, rem) + j;
+}
+
+// One sweep over one lattice.
+template <int BX, int MODE, int PF, int FORCE, int ST, int COLL>
 __global__ __launch_bounds__(BX) void sweep_kernel(const void *__restrict__ src,
                                                    void *__restrict__ dst, Coeffs c, Tiles tl,
                                                    long long t,
@@ -552,8 +630,8 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const void *__restrict__ src,
                                                    Fields fo, double *__restrict__ rho_snap,
                                                    double *__restrict__ partials)
 {
-    sweep_tile<BX, MODE, PF, FORCE, ST>(src, dst, c, tl, blockIdx.x, t, err, fo, rho_snap,
-                                        partials);
+    sweep_tile<BX, MODE, PF, FORCE, ST, COLL>(src, dst, c, tl, xcd_tile(blockIdx.x, tl.ntiles),
+                                              t, err, fo, rho_snap, partials);
 }
 
 // One lattice of a batch, as the batched step kernel sees it.
@@ -566,12 +644,12 @@ struct BatchEntry {
     int tile0;                // its first tile in the batch grid
 };
 
-// One time step of every lattice of a batch: workgroup b runs tile
-// b - tile0 of the lattice whose tile range holds b (binary search over the
-// table, uniform per workgroup).  The step count since the table was written
+// One time step of every lattice of a batch: workgroup b takes batch tile
+// xcd_tile(b) and runs tile b - tile0 of the lattice whose tile range holds
+// it (binary search over the table, uniform per workgroup).  The step count since the table was written
 // is read from d_steps (so that a captured graph replays correctly); its
 // parity selects the source buffer.
-template <int BX, int PF, int FORCE, int ST>
+template <int BX, int PF, int FORCE, int ST, int COLL>
 __global__ __launch_bounds__(BX) void batch_step_kernel(const BatchEntry *__restrict__ table,
                                                         int nlat,
                                                         const long long *__restrict__ d_steps)
@@ -579,16 +657,16 @@ __global__ __launch_bounds__(BX) void batch_step_kernel(const BatchEntry *__rest
     const long long steps = *d_steps;
     const int parity = (int)(steps & 1);
     int lo = 0, hi = nlat - 1;
-    const int b = blockIdx.x;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (table[mid].tile0 <= b) lo = mid;
         else hi = mid - 1;
     }
     const BatchEntry &e = table[lo];
-    sweep_tile<BX, kStep, PF, FORCE, ST>(e.buf[parity], (void *)e.buf[parity ^ 1], e.c, e.tl,
-                                         b - e.tile0, e.t0 + steps, e.err, Fields{},
-                                         nullptr, nullptr);
+    sweep_tile<BX, kStep, PF, FORCE, ST, COLL>(e.buf[parity], (void *)e.buf[parity ^ 1], e.c,
+                                               e.tl, b - e.tile0, e.t0 + steps, e.err, Fields{},
+                                               nullptr, nullptr);
 }
 
 __global__ void bump_counter(long long *p) { *p += 1; }
@@ -720,7 +798,7 @@ struct lbm_batch {
     std::vector<void *> cur_at_upload, nxt_at_upload;
     long long steps_since_upload;
     bool table_valid;
-    int storage, force_on;
+    int storage, force_on, coll;
     int bx, rows;
     int total_tiles;
     hipGraphExec_t graph;     // kGraphSteps batched steps, valid with the table
@@ -786,6 +864,13 @@ bool params_valid(const lbm_params *p, std::string *why)
         p->storage != LBM_STORE_F16_SHIFTED)
         return fail("unknown storage mode");
     if (!std::isfinite(p->rho_ref)) return fail("rho_ref not finite");
+    if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_MRT)
+        return fail("unknown collision operator");
+    if (p->collision == LBM_COLL_MRT) {
+        const double taus[5] = {p->tau_rho, p->tau_e, p->tau_zeta, p->tau_j, p->tau_q};
+        for (double v : taus)
+            if (!(v > 0.5) || !std::isfinite(v)) return fail("MRT relaxation times must be > 0.5");
+    }
     return true;
 }
 
@@ -806,6 +891,10 @@ Coeffs make_coeffs(const lbm_params *p, size_t pitch, size_t plane)
     c.cA = 9.0 * p->G * (1.5 * p->epsilon - p->sigma + 1.0);
     c.cB = 9.0 * p->G * (p->sigma - 1.0);
     c.rho_ref = p->storage == LBM_STORE_F64 ? 0.0 : p->rho_ref;
+    c.coll = p->collision;
+    c.s_e = p->collision == LBM_COLL_MRT ? 1.0 / p->tau_e : 0.0;
+    c.s_z = p->collision == LBM_COLL_MRT ? 1.0 / p->tau_zeta : 0.0;
+    c.s_q = p->collision == LBM_COLL_MRT ? 1.0 / p->tau_q : 0.0;
     c.force_on = p->force_on;
     c.trace_alt = p->m2_trace_alt;
     c.storage = p->storage;
@@ -834,11 +923,11 @@ bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl,
 // Default launch shape: 256-thread workgroups unless another width wastes
 // clearly fewer lanes on ragged strips (small lattices), then row segments
 // short enough for about 64 waves per CU on 256 CUs (20 for FP16 storage),
-// each segment at least 7 rows (FP64) or 5 rows (FP32, FP16).  Many short
+// each segment at least 8 rows (FP64) or 5 rows (FP32, FP16).  Many short
 // segments keep more rows of loads in flight per CU (each segment starts with
 // a burst of three row loads); their halo rows come back mostly from cache.
 // Measured on 2048 x 2048 in sweeps over 128..512 threads and 3..25 rows:
-// FP64 is fastest at (256 threads, 7 rows), FP32 at (256, 5), FP16 at
+// FP64 is fastest at (256 threads, 8 rows), FP32 at (256, 5..8), FP16 at
 // (256, 17).
 void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
 {
@@ -861,7 +950,7 @@ void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
     int nseg = (int)std::ceil(target_waves / ((double)tb.nstrips * (best / 64)));
     nseg = std::max(1, std::min(nseg, ny));
     int rows = (ny + nseg - 1) / nseg;
-    rows = std::max(rows, std::min(storage == LBM_STORE_F64 ? 7 : 5, ny));
+    rows = std::max(rows, std::min(storage == LBM_STORE_F64 ? 8 : 5, ny));
     while ((long long)tb.nstrips * ((ny + rows - 1) / rows) > kMaxTiles)
         ++rows;
     *bx_out = best;
@@ -876,7 +965,7 @@ lbm_status dev_fail(lbm_handle *h, hipError_t e, const char *what)
     return LBM_ERR_DEVICE;
 }
 
-template <int MODE, int FORCE, int ST>
+template <int MODE, int FORCE, int ST, int COLL>
 hipError_t launch_sweep_t(lbm_handle *h, const void *src, void *dst, Fields fo)
 {
     const dim3 grid((unsigned)h->tiles.ntiles);
@@ -885,7 +974,7 @@ hipError_t launch_sweep_t(lbm_handle *h, const void *src, void *dst, Fields fo)
     switch (h->bx) {
 #define LBM_CASE(BX)                                                                          \
     case BX:                                                                                  \
-        hipLaunchKernelGGL((sweep_kernel<BX, MODE, PF, FORCE, ST>), grid, dim3(BX), 0,         \
+        hipLaunchKernelGGL((sweep_kernel<BX, MODE, PF, FORCE, ST, COLL>), grid, dim3(BX), 0,   \
                            h->stream, src, dst, c, h->tiles, (long long)h->t, h->err, fo,     \
                            h->rho_snap, h->partials);                                         \
         break;
@@ -904,15 +993,26 @@ hipError_t launch_sweep_t(lbm_handle *h, const void *src, void *dst, Fields fo)
     return hipGetLastError();
 }
 
+// The collision operator enters only the step sweep.
+template <int MODE, int FORCE, int ST>
+hipError_t launch_sweep_c(lbm_handle *h, const void *src, void *dst, Fields fo)
+{
+    if constexpr (MODE == kStep) {
+        if (h->c.coll == LBM_COLL_MRT)
+            return launch_sweep_t<MODE, FORCE, ST, LBM_COLL_MRT>(h, src, dst, fo);
+    }
+    return launch_sweep_t<MODE, FORCE, ST, LBM_COLL_BGK>(h, src, dst, fo);
+}
+
 template <int MODE, int FORCE>
 hipError_t launch_sweep_f(lbm_handle *h, const void *src, void *dst, Fields fo)
 {
     switch (h->c.storage) {
-    case LBM_STORE_F64: return launch_sweep_t<MODE, FORCE, LBM_STORE_F64>(h, src, dst, fo);
+    case LBM_STORE_F64: return launch_sweep_c<MODE, FORCE, LBM_STORE_F64>(h, src, dst, fo);
     case LBM_STORE_F32_SHIFTED:
-        return launch_sweep_t<MODE, FORCE, LBM_STORE_F32_SHIFTED>(h, src, dst, fo);
+        return launch_sweep_c<MODE, FORCE, LBM_STORE_F32_SHIFTED>(h, src, dst, fo);
     case LBM_STORE_F16_SHIFTED:
-        return launch_sweep_t<MODE, FORCE, LBM_STORE_F16_SHIFTED>(h, src, dst, fo);
+        return launch_sweep_c<MODE, FORCE, LBM_STORE_F16_SHIFTED>(h, src, dst, fo);
     }
     return hipErrorInvalidValue;
 }
@@ -983,7 +1083,7 @@ lbm_status read_sticky(lbm_handle *h)
 }
 
 
-template <int FORCE, int ST>
+template <int FORCE, int ST, int COLL>
 hipError_t launch_batch_t(lbm_batch *b)
 {
     const dim3 grid((unsigned)b->total_tiles);
@@ -991,8 +1091,8 @@ hipError_t launch_batch_t(lbm_batch *b)
     switch (b->bx) {
 #define LBM_CASE(BX)                                                                          \
     case BX:                                                                                  \
-        hipLaunchKernelGGL((batch_step_kernel<BX, kPrefetch, FORCE, ST>), grid, dim3(BX), 0,   \
-                           b->stream, b->d_table, nlat, b->d_steps);                          \
+        hipLaunchKernelGGL((batch_step_kernel<BX, kPrefetch, FORCE, ST, COLL>), grid, dim3(BX), \
+                           0, b->stream, b->d_table, nlat, b->d_steps);                       \
         break;
         LBM_CASE(64)
         LBM_CASE(128)
@@ -1009,13 +1109,20 @@ hipError_t launch_batch_t(lbm_batch *b)
     return hipGetLastError();
 }
 
+template <int FORCE, int ST>
+hipError_t launch_batch_c(lbm_batch *b)
+{
+    return b->coll == LBM_COLL_MRT ? launch_batch_t<FORCE, ST, LBM_COLL_MRT>(b)
+                                   : launch_batch_t<FORCE, ST, LBM_COLL_BGK>(b);
+}
+
 template <int FORCE>
 hipError_t launch_batch_f(lbm_batch *b)
 {
     switch (b->storage) {
-    case LBM_STORE_F64: return launch_batch_t<FORCE, LBM_STORE_F64>(b);
-    case LBM_STORE_F32_SHIFTED: return launch_batch_t<FORCE, LBM_STORE_F32_SHIFTED>(b);
-    case LBM_STORE_F16_SHIFTED: return launch_batch_t<FORCE, LBM_STORE_F16_SHIFTED>(b);
+    case LBM_STORE_F64: return launch_batch_c<FORCE, LBM_STORE_F64>(b);
+    case LBM_STORE_F32_SHIFTED: return launch_batch_c<FORCE, LBM_STORE_F32_SHIFTED>(b);
+    case LBM_STORE_F16_SHIFTED: return launch_batch_c<FORCE, LBM_STORE_F16_SHIFTED>(b);
     }
     return hipErrorInvalidValue;
 }
@@ -1372,6 +1479,7 @@ lbm_status lbm_batch_create(int32_t capacity, void *d_workspace, size_t workspac
     b->table_valid = false;
     b->storage = -1;
     b->force_on = -1;
+    b->coll = -1;
     b->bx = 256;
     b->rows = 5;
     b->total_tiles = 0;
@@ -1390,12 +1498,14 @@ lbm_status lbm_batch_add(lbm_batch *b, lbm_handle *h)
     for (lbm_handle *m : b->members)
         if (m == h) return LBM_ERR_INVALID_ARG;
     if (!b->members.empty() &&
-        (h->p.storage != b->storage || h->p.force_on != b->force_on || h->stream != b->stream))
+        (h->p.storage != b->storage || h->p.force_on != b->force_on ||
+         h->p.collision != b->coll || h->stream != b->stream))
         return LBM_ERR_INVALID_ARG;
     if (b->members.empty()) {
         if (h->stream != b->stream) return LBM_ERR_INVALID_ARG;
         b->storage = h->p.storage;
         b->force_on = h->p.force_on;
+        b->coll = h->p.collision;
     }
     b->members.push_back(h);
     b->table_valid = false;

@@ -2,10 +2,10 @@
 //
 // Host-side scheduler: a FIFO queue of submitted jobs, admission by device
 // memory footprint into a caller-owned arena (first-fit, arena.h), one batch
-// per (storage mode, force switch) advanced by the batched step, and
-// retirement with the results copied to the caller's host buffers.  Every
-// device operation goes through the public C ABI of lbm.h plus plain HIP
-// copies on the server's stream.
+// per (storage mode, force switch, collision operator) advanced by the
+// batched step, and retirement with the results copied to the caller's host
+// buffers.  Every device operation goes through the public C ABI of lbm.h
+// plus plain HIP copies on the server's stream.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -22,6 +22,8 @@
 namespace {
 
 constexpr int kStorages = 3;
+// one batch per (storage mode, force switch, collision operator)
+constexpr int kBatchKeys = kStorages * 2 * 2;
 
 struct Job {
     int64_t id;
@@ -37,7 +39,10 @@ struct Job {
 
 size_t cells(const lbm_params &p) { return (size_t)p.nx * (size_t)p.ny; }
 
-int batch_key(const lbm_params &p) { return p.storage * 2 + (p.force_on ? 1 : 0); }
+int batch_key(const lbm_params &p)
+{
+    return (p.storage * 2 + (p.force_on ? 1 : 0)) * 2 + (p.collision == LBM_COLL_MRT ? 1 : 0);
+}
 
 size_t buffer_bytes(const lbm_params &p, bool want_f) { return (want_f ? 9 : 1) * cells(p) * 8; }
 
@@ -48,7 +53,7 @@ struct lbm_server {
     char *arena_base;
     lbm_arena::Arena arena;
     hipStream_t stream;
-    lbm_batch *batches[2 * kStorages];
+    lbm_batch *batches[kBatchKeys];
     std::list<Job *> queue;
     std::vector<Job *> resident;
     std::vector<std::pair<int64_t, int32_t>> done;
@@ -140,7 +145,7 @@ lbm_status admit(lbm_server *s)
 
 lbm_status step_batches(lbm_server *s)
 {
-    for (int key = 0; key < 2 * kStorages; ++key) {
+    for (int key = 0; key < kBatchKeys; ++key) {
         int64_t n = s->cfg.quantum;
         bool any = false;
         for (Job *j : s->resident)
@@ -218,7 +223,7 @@ lbm_status lbm_server_create(const lbm_server_config *cfg, void *d_arena, size_t
     s->stream = (hipStream_t)hip_stream;
     std::memset(s->batches, 0, sizeof(s->batches));
     const size_t tb = lbm_batch_workspace_bytes(cfg->max_resident);
-    for (int key = 0; key < 2 * kStorages; ++key) {
+    for (int key = 0; key < kBatchKeys; ++key) {
         size_t off;
         lbm_status st = s->arena.alloc(tb, &off) ? LBM_OK : LBM_ERR_OOM;
         if (st == LBM_OK)

@@ -27,6 +27,8 @@ LBM_ERR_STATE = -5
 LBM_STORE_F64 = 0
 LBM_STORE_F32_SHIFTED = 1
 LBM_STORE_F16_SHIFTED = 2
+LBM_COLL_BGK = 0
+LBM_COLL_MRT = 1
 
 _ALIGN = 256
 
@@ -40,6 +42,9 @@ class lbm_params(ctypes.Structure):
         ("eos_c", ctypes.c_double), ("eos_k", ctypes.c_double), ("T", ctypes.c_double),
         ("force_on", ctypes.c_int32), ("m2_trace_alt", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("rho_ref", ctypes.c_double),
+        ("collision", ctypes.c_int32),
+        ("tau_rho", ctypes.c_double), ("tau_e", ctypes.c_double), ("tau_zeta", ctypes.c_double),
+        ("tau_j", ctypes.c_double), ("tau_q", ctypes.c_double),
     ]
 
 
@@ -165,7 +170,10 @@ def make_params(p: dict) -> lbm_params:
                       float(p["epsilon"]), float(p["sigma"]), float(p["eos_a"]),
                       float(p["eos_b"]), float(p["eos_c"]), float(p["eos_k"]), float(p["T"]),
                       int(bool(p.get("force_on", True))), int(bool(p.get("m2_trace_alt", False))),
-                      int(p.get("storage", LBM_STORE_F64)), float(p.get("rho_ref", 0.0)))
+                      int(p.get("storage", LBM_STORE_F64)), float(p.get("rho_ref", 0.0)),
+                      int(p.get("collision", LBM_COLL_BGK)),
+                      *[float(p.get(k, 1.0)) for k in ("tau_rho", "tau_e", "tau_zeta", "tau_j",
+                                                       "tau_q")])
 
 
 def _dev_ptr(t):

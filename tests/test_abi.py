@@ -56,6 +56,17 @@ def test_workspace_size_and_validation(lib):
         q = lbm.make_params(W.params(64, 48, tr=0.8))
         setattr(q, field, value)
         assert lib.lbm_workspace_bytes(ctypes.byref(q)) == 0, field
+    m = lbm.make_params(W.params(64, 48, tr=0.8, collision="mrt", mrt=(1.0, 0.9, 1.1, 1.0, 1.2)))
+    assert lib.lbm_workspace_bytes(ctypes.byref(m)) == n
+    for field, value in (("collision", 2), ("tau_e", 0.5), ("tau_q", float("nan")),
+                         ("tau_rho", 0.4)):
+        q = lbm.make_params(W.params(64, 48, tr=0.8, collision="mrt"))
+        setattr(q, field, value)
+        assert lib.lbm_workspace_bytes(ctypes.byref(q)) == 0, field
+    # the MRT relaxation times are not read for BGK
+    q = lbm.make_params(W.params(64, 48, tr=0.8))
+    q.tau_e = 0.1
+    assert lib.lbm_workspace_bytes(ctypes.byref(q)) == n
     h = ctypes.c_void_p()
     st = lib.lbm_init(ctypes.byref(p), None, 0, None, None, None, None, ctypes.byref(h))
     assert st == lbm.LBM_ERR_INVALID_ARG and not h.value

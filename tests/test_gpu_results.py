@@ -1,0 +1,150 @@
+"""Result-level errors of the reduced-precision storage modes (populations
+kept as FP32 or FP16 deviations from w_i rho_ref, FP32 arithmetic) against
+FP64, per result:
+
+  * droplet oscillation (Sec. IV.C): 1024 x 1024 periodic lattice, elliptical
+    droplet with semi-axes 160 (x) and 120 (y), T_r = 0.7, W = 2, BGK with
+    tau in {0.6, 0.8, 1.0}, 40000 steps; the +x extent of the droplet through
+    its centre is sampled every 20 steps and a damped cosine gives the period
+    (the paper samples the extremity, every 100 steps); mass drift from the
+    FP64 diagnostics sums;
+  * Laplace pressure jump (Sec. IV.B): static droplets of four radii on
+    128 x 128 lattices at T_r = 0.8, Delta P = P(rho_in) - P(rho_out) with the
+    EOS of Eq. CSEOS, and the surface tension from the slope of Delta P
+    against 1/R.
+
+The FP64 results come from the FP64 GPU path, which matches the CPU oracle
+to 1e-12 per field (test_gpu_parity.py); running these sizes and horizons on
+the oracle would take hours.  The measured errors are logged.
+
+FP16 storage with one reference density for the whole lattice does not
+reproduce the oscillation: collision increments smaller than half a binary16
+ulp of the liquid's stored deviations are lost, the droplet's shape drifts by
+many cells and the period comes out several percent to tens of percent off
+(the fit fails outright at tau = 1).  Its period is logged, not asserted;
+its mass drift and Laplace errors are asserted at the measured level.  The
+FP16 numbers are a property of the format with a global shift, not of the
+kernel: test_gpu_storage.py shows the kernel agreeing with the FP64 oracle
+run with the same binary16 rounding."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import analytics as A
+from paper_2003_07968_amd import lbm
+from paper_2003_07968_amd import workloads as W
+
+from .gpu_common import log, require_gpu
+from .helpers import droplet_measure, fit_damped_period, x_extent
+
+pytestmark = pytest.mark.gpu
+
+OSC_STEPS, OSC_EVERY = 40000, 20
+_osc_cache = {}
+
+
+def _oscillation(tau, storage):
+    key = (tau, storage)
+    if key in _osc_cache:
+        return _osc_cache[key]
+    p, rho0 = W.ellipse_case(n=1024, tr=0.7, tau=tau)
+    rg, rl = W.unit_cs_coexistence(0.7)
+    rho_m = 0.5 * (rg + rl)
+    p["storage"] = W.STORAGE[storage]
+    p["rho_ref"] = W.shift_reference(rho0, storage)
+    lat = lbm.Lattice(p, rho0)
+    rho = torch.empty((1024, 1024), dtype=torch.float64, device="cuda")
+    m0 = lat.diagnostics()["mass"]
+    ts, rs = [], []
+    for k in range(OSC_STEPS // OSC_EVERY + 1):
+        if k:
+            lat.step(OSC_EVERY)
+        lbm.lbm_moments(lat.handle, rho=rho)
+        ts.append(k * OSC_EVERY)
+        rs.append(x_extent(rho[511:513].cpu().numpy(), rho_m))
+    drift = abs(lat.diagnostics()["mass"] / m0 - 1)
+    lat.sync()
+    try:
+        T, popt = fit_damped_period(ts, rs)
+    except RuntimeError:          # no oscillation the fit can follow
+        T, popt = float("nan"), [float("nan")] * 5
+    out = {"T": T, "drift": drift, "r": np.array(rs), "decay": popt[2]}
+    _osc_cache[key] = out
+    return out
+
+
+# Tolerances of the reduced-precision results against FP64 (period: relative;
+# extent: lattice units, max over the time series; drift: |dM|/M at 40000
+# steps), a few times the measured worst case over tau in {0.6, 0.8, 1.0}:
+#   FP32: period 4.3e-4, extent 0.041 cells, drift 2.2e-4 (tau = 0.6);
+#   FP16: drift 2.0e-2 (period and extent not asserted, see above);
+#   FP64: drift 2.9e-12 (mass is conserved to rounding).
+PERIOD_TOL = {"f32": 2e-3}
+EXTENT_TOL = {"f32": 0.2}
+DRIFT_TOL = {"f64": 1e-11, "f32": 1e-3, "f16": 5e-2}
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0])
+def test_oscillation_period_and_mass_drift(tau):
+    require_gpu()
+    ref = _oscillation(tau, "f64")
+    rg, rl = W.unit_cs_coexistence(0.7)
+    T = 0.7 * W.UNIT_CS_TC
+    gamma = A.planar_surface_tension_quad(A.UNIT_EOS, T, 1.73, 1.0)
+    Ta = A.lamb_period(gamma, rl, 160.0, 120.0)
+    log(f"tau={tau}: f64 period {ref['T']:.1f} (Lamb {Ta:.1f}, {ref['T'] / Ta - 1:+.3f}), "
+        f"mass drift {ref['drift']:.2e}")
+    assert ref["drift"] <= DRIFT_TOL["f64"]
+    for st in ("f32", "f16"):
+        res = _oscillation(tau, st)
+        e_T = abs(res["T"] / ref["T"] - 1)
+        e_r = float(np.abs(res["r"] - ref["r"]).max())
+        log(f"  {st}: period {res['T']:.1f} (rel err {e_T:.2e}), extent max err {e_r:.3f}, "
+            f"mass drift {res['drift']:.2e}")
+        if st in PERIOD_TOL:
+            assert e_T <= PERIOD_TOL[st]
+            assert e_r <= EXTENT_TOL[st]
+        assert res["drift"] <= DRIFT_TOL[st]
+
+
+LAPLACE_RADII = (16.0, 22.0, 28.0, 34.0)
+# relative errors against FP64; measured: FP32 1.2e-4 per radius and 2.7e-6 on
+# the fitted slope, FP16 0.13 and 0.099
+DP_TOL = {"f32": 1e-3, "f16": 0.3}
+GAMMA_TOL = {"f32": 1e-4, "f16": 0.2}
+
+
+def _laplace(storage, n=128, tr=0.8, steps=16000):
+    T = tr * W.UNIT_CS_TC
+    rg, rl = W.unit_cs_coexistence(tr)
+    rows = []
+    for R0 in LAPLACE_RADII:
+        p = W.params(n, n, tr=tr, tau=1.0, storage=storage)
+        rho0 = W.droplet(n, n, R0, rl, rg, 2.0)
+        p["rho_ref"] = W.shift_reference(rho0, storage)
+        lat = lbm.Lattice(p, rho0)
+        lat.step(steps)
+        lat.sync()
+        rho = lat.moments()["rho"].cpu().numpy()
+        R, rin, rout = droplet_measure(rho, 8.0)
+        rows.append((R, A.UNIT_EOS.P(rin, T) - A.UNIT_EOS.P(rout, T)))
+    R = np.array([r for r, _ in rows])
+    dP = np.array([d for _, d in rows])
+    gamma, _ = np.polyfit(1.0 / R, dP, 1)
+    return R, dP, gamma
+
+
+def test_laplace_pressure_vs_fp64():
+    require_gpu()
+    R64, dP64, g64 = _laplace("f64")
+    T = 0.8 * W.UNIT_CS_TC
+    g_pi = A.planar_surface_tension_quad(A.UNIT_EOS, T, 1.73, 1.0)
+    log(f"f64: R {np.round(R64, 2)}, dP {dP64}, gamma {g64:.5f} (planar {g_pi:.5f})")
+    for st in ("f32", "f16"):
+        R, dP, g = _laplace(st)
+        e_dp = float(np.max(np.abs(dP / dP64 - 1)))
+        e_g = abs(g / g64 - 1)
+        log(f"  {st}: dP rel err max {e_dp:.2e}, gamma {g:.5f} (rel err {e_g:.2e}), "
+            f"R err max {np.abs(R - R64).max():.3f}")
+        assert e_dp <= DP_TOL[st]
+        assert e_g <= GAMMA_TOL[st]

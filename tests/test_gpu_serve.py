@@ -15,6 +15,10 @@ from .helpers import oracle_params
 
 pytestmark = pytest.mark.gpu
 
+# the server keeps one batch (and its table in the arena) per storage mode,
+# force switch and collision operator
+BATCH_KEYS = 3 * 2 * 2
+
 
 def _jobs(count, seed, storages=("f64", "f32", "f16"), sides=(24, 96), steps=(0, 150)):
     """Seeded mixed jobs: droplet or slab, random T_r, sigma, tau, storage."""
@@ -82,7 +86,7 @@ def test_results_same_alone_and_in_the_mix():
             assert np.array_equal(f, f_a), job
     s = srv.stats()
     log(f"  stats: {s}")
-    tables = 6 * ((lbm.lbm_batch_workspace_bytes(6) + 255) // 256 * 256)
+    tables = BATCH_KEYS * ((lbm.lbm_batch_workspace_bytes(6) + 255) // 256 * 256)
     assert s["completed"] == len(jobs) and s["arena_used"] == tables  # all jobs' memory back
 
 
@@ -113,7 +117,7 @@ def test_admission_by_footprint():
         p["storage"], p["rho_ref"] = 1, W.shift_reference(r, "f32")
         jobs.append((p, r, 30 + 7 * k))
     need = [lbm.lbm_server_job_bytes(lbm.make_params(p)) for p, _, _ in jobs]
-    tables = 6 * ((lbm.lbm_batch_workspace_bytes(8) + 255) // 256 * 256)
+    tables = BATCH_KEYS * ((lbm.lbm_batch_workspace_bytes(8) + 255) // 256 * 256)
     arena = tables + 2 * max(need) + 1024   # room for two jobs at a time, not three
     srv = lbm.Server(arena_bytes=arena, max_resident=8, quantum=8, max_bypass=0)
     for p, r, n in jobs:
