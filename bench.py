@@ -44,7 +44,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-BYTES_PER_CELL = {"f64": 144, "f32": 72, "f16": 36}  # 9 reads + 9 writes per cell update
+# 9 reads + 9 writes per cell update (and, for f16l, the per-cell FP32 reference)
+BYTES_PER_CELL = {"f64": 144, "f32": 72, "f16": 36, "f16l": 44}
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 METRIC = "MLUPS/GPU and % HBM roofline (FP64 vs FP32/FP16-shifted); p50/p99 time-to-result"
 N = 2048
@@ -411,7 +412,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
-                  "f16": "f32 arithmetic, f16-shifted storage"}[args.storage],
+                  "f16": "f32 arithmetic, f16-shifted storage",
+                  "f16l": "f32 arithmetic, f16 storage with per-cell f32 reference"}[args.storage],
         "data": "synthetic",
         "config": {
             "workload": "D2Q9 2048x2048 periodic flat slab, T_r in {0.6,0.7,0.8,0.9} "

@@ -80,8 +80,16 @@ typedef enum {
     LBM_STORE_F64 = 0,         /* populations stored in FP64, FP64 arithmetic           */
     LBM_STORE_F32_SHIFTED = 1, /* stored as FP32 deviations f_i - w_i rho_ref, FP32
                                   arithmetic (72 bytes per cell update)                */
-    LBM_STORE_F16_SHIFTED = 2  /* stored as FP16 (IEEE binary16) deviations, FP32
+    LBM_STORE_F16_SHIFTED = 2, /* stored as FP16 (IEEE binary16) deviations, FP32
                                   arithmetic (36 bytes per cell update)                */
+    LBM_STORE_F16_LOCAL = 3    /* stored as FP16 deviations from w_i R(z), where R(z) is
+                                  a per-cell FP32 reference density of the sending cell
+                                  z: R = sum_i f*_i, X_i = round16(f*_i - w_i R), then R
+                                  corrected by the nine rounding errors and rounded to
+                                  FP32, so that the cell's mass is kept to FP32
+                                  rounding; FP32 arithmetic (44 bytes per cell update:
+                                  9 x 2 + 4 read, as much written).  rho_ref is not
+                                  used.                                                */
 } lbm_storage;
 
 /* Physical and numerical parameters, named as in the paper. */
@@ -121,9 +129,10 @@ typedef struct lbm_handle lbm_handle;
 
 /* Bytes of device workspace lbm_init needs for these parameters (0 if they are
  * invalid).  The workspace holds two population copies (2 * 9 * nx * ny
- * elements of the storage type, rows padded to 128 bytes), a density snapshot
- * for the steady-state criterion (FP64), 1.5 MB of reduction scratch and the
- * error word. */
+ * elements of the storage type, rows padded to 128 bytes; with
+ * LBM_STORE_F16_LOCAL each copy also holds nx * ny FP32 reference densities),
+ * a density snapshot for the steady-state criterion (FP64), 1.5 MB of
+ * reduction scratch and the error word. */
 size_t lbm_workspace_bytes(const lbm_params *params);
 
 /* Validate params, carve the workspace (device memory of at least
@@ -168,8 +177,12 @@ lbm_status lbm_get_populations(lbm_handle *h, double *d_f);
 
 /* Replace the state by f(t) = d_f ([9][ny][nx] FP64, device) and set the
  * time counter to t >= 0 (checkpoint restart).  With shifted storage each
- * f_i - w_i rho_ref is rounded to the storage type.  Synchronous.  Clears
- * nothing else: a sticky error stays. */
+ * f_i - w_i rho_ref is rounded to the storage type, so a state read with
+ * lbm_get_populations comes back bitwise.  With LBM_STORE_F16_LOCAL each
+ * cell's nine values are encoded afresh against their own sum; the rounded
+ * deviations of a stored state need not sum to zero, so a value may move by
+ * about one binary16 rounding of its deviation (restart close, not bitwise).
+ * Synchronous.  Clears nothing else: a sticky error stays. */
 lbm_status lbm_set_populations(lbm_handle *h, const double *d_f, int64_t t);
 
 /* Number of completed steps. */

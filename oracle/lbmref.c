@@ -65,10 +65,38 @@ double lbmref_quantize(int32_t storage, double x)
     return x;
 }
 
-/* Reduced-precision storage: f_i = w_i rho_ref + round(f_i - w_i rho_ref). */
+/* Storage mode 3: the nine values f[i * n + k] that cell k sends are kept as
+ * binary16 deviations from w_i R with R = sum_i f_i, R corrected by the
+ * rounding errors and rounded to binary32. */
+static void store_round_local(double *f, size_t n)
+{
+#pragma omp parallel for schedule(static)
+    for (size_t k = 0; k < n; ++k) {
+        double R = 0.0;
+        for (int i = 0; i < 9; ++i)
+            R += f[(size_t)i * n + k];
+        double X[9], err = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            double dev = f[(size_t)i * n + k] - W[i] * R;
+            X[i] = lbmref_quantize(2, dev);
+            err += dev - X[i];
+        }
+        double Rs = lbmref_quantize(1, R + err);
+        for (int i = 0; i < 9; ++i)
+            f[(size_t)i * n + k] = X[i] + W[i] * Rs;
+    }
+}
+
+/* Reduced-precision storage: f_i = w_i rho_ref + round(f_i - w_i rho_ref), or
+ * the per-cell form of mode 3.  f holds post-collision values indexed by the
+ * cell that sends them. */
 static void store_round(const lbmref_params *p, double *f, size_t n)
 {
     if (!p->storage) return;
+    if (p->storage == 3) {
+        store_round_local(f, n);
+        return;
+    }
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < 9; ++i)
         for (size_t k = 0; k < n; ++k) {
@@ -351,7 +379,7 @@ static int check_params(const lbmref_params *p)
     if (!p || p->nx < 3 || p->ny < 3) return LBMREF_ERR_INVALID_ARG;
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return LBMREF_ERR_INVALID_ARG;
     if (!(p->G != 0.0) || !isfinite(p->G)) return LBMREF_ERR_INVALID_ARG;
-    if (p->storage < 0 || p->storage > 2 || !isfinite(p->rho_ref)) return LBMREF_ERR_INVALID_ARG;
+    if (p->storage < 0 || p->storage > 3 || !isfinite(p->rho_ref)) return LBMREF_ERR_INVALID_ARG;
     if (p->collision != 0 && p->collision != 1) return LBMREF_ERR_INVALID_ARG;
     if (p->collision == 1) {
         const double taus[5] = {p->tau_rho, p->tau_e, p->tau_zeta, p->tau_j, p->tau_q};
@@ -373,6 +401,25 @@ int lbmref_init(const lbmref_params *p, const double *rho0, const double *ux0,
         lbmref_equilibrium(rho0[k], ux0 ? ux0[k] : 0.0, uy0 ? uy0[k] : 0.0, feq);
         for (int i = 0; i < 9; ++i)
             f[(size_t)i * n + k] = feq[i];
+    }
+    if (p->storage == 3) {
+        /* group the values by the cell z = x - c_i that streams them to x */
+        double *g = malloc(9 * n * sizeof(double));
+        if (!g) return LBMREF_ERR_INVALID_ARG;
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x)
+                for (int i = 0; i < 9; ++i)
+                    g[(size_t)i * n + (size_t)y * p->nx + x] =
+                        f[(size_t)i * n + (size_t)wrap(y + CY[i], p->ny) * p->nx +
+                          wrap(x + CX[i], p->nx)];
+        store_round(p, g, n);
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x)
+                for (int i = 0; i < 9; ++i)
+                    f[(size_t)i * n + (size_t)wrap(y + CY[i], p->ny) * p->nx +
+                      wrap(x + CX[i], p->nx)] = g[(size_t)i * n + (size_t)y * p->nx + x];
+        free(g);
+        return LBMREF_OK;
     }
     store_round(p, f, n);
     return LBMREF_OK;

@@ -46,7 +46,15 @@ typedef struct {
     int32_t storage;      /* 0: exact FP64 state; 1, 2: the state is kept as
                              deviations f_i - w_i rho_ref rounded to IEEE
                              binary32 (1) or binary16 (2) after every step and
-                             at initialisation (reduced-precision storage)    */
+                             at initialisation (reduced-precision storage);
+                             3: per source cell z, the nine post-collision
+                             values are kept as binary16 deviations
+                             X_i = round16(f*_i - w_i R) from w_i times the
+                             cell's own FP32 reference R = sum_i f*_i, with R
+                             then corrected by the rounding errors,
+                             R <- round32(R + sum_i (f*_i - w_i R - X_i)), so
+                             that sum_i (X_i + w_i R) keeps the cell's mass;
+                             f*_i becomes X_i + w_i R                           */
     double rho_ref;       /* reference density of the stored deviations       */
     int32_t collision;    /* 0: BGK (Eq. BGKCO) with the Guo factor of
                              Eq. GFSBGK; 1: MRT (Eq. MRTCO) with the Guo

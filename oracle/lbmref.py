@@ -93,7 +93,7 @@ def _ptr(a):
     return a.ctypes.data_as(_DP)
 
 
-STORE_F64, STORE_F32, STORE_F16 = 0, 1, 2
+STORE_F64, STORE_F32, STORE_F16, STORE_F16_LOCAL = 0, 1, 2, 3
 
 
 COLL_BGK, COLL_MRT = 0, 1

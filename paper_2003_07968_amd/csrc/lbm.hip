@@ -11,8 +11,9 @@
 //
 // Storage modes: FP64 populations with FP64 arithmetic, or populations kept
 // as deviations d_i = f_i - w_i rho_ref in FP32 or FP16 with FP32 arithmetic
-// (rho_ref is a reference density, normally the mean).  The diagnostics
-// reductions are FP64 in every mode.
+// (rho_ref is a reference density, normally the mean), or as FP16 deviations
+// from w_i R(z) with a per-cell FP32 reference R (the nine values a cell sends
+// share its R).  The diagnostics reductions are FP64 in every mode.
 //
 // Kernel design (one fused pass per step, HBM-bound):
 //   * populations are arrays X_i[y][x] holding the post-collision values of
@@ -64,19 +65,32 @@ template <int ST> struct Store;
 template <> struct Store<LBM_STORE_F64> {
     using E = double;  // stored element
     using R = double;  // arithmetic
+    static constexpr bool local = false;  // per-cell reference density
 };
 template <> struct Store<LBM_STORE_F32_SHIFTED> {
     using E = float;
     using R = float;
+    static constexpr bool local = false;
 };
 template <> struct Store<LBM_STORE_F16_SHIFTED> {
     using E = _Float16;
     using R = float;
+    static constexpr bool local = false;
+};
+template <> struct Store<LBM_STORE_F16_LOCAL> {
+    using E = _Float16;
+    using R = float;
+    static constexpr bool local = true;
 };
 
 size_t elem_size(int storage)
 {
     return storage == LBM_STORE_F64 ? 8 : (storage == LBM_STORE_F32_SHIFTED ? 4 : 2);
+}
+
+bool is_f16(int storage)
+{
+    return storage == LBM_STORE_F16_SHIFTED || storage == LBM_STORE_F16_LOCAL;
 }
 
 // Coefficients of one lattice, precomputed on the host.
@@ -95,7 +109,10 @@ struct Coeffs {
     // cSC = -2G/cs^2 = -6G; cA = (3/2 eps - (sigma - 1)) cs^2 G / cs^6
     // = 9G (1.5 eps - sigma + 1); cB = (sigma - 1) cs^2 G / cs^6 = 9G (sigma - 1).
     double cSC, cA, cB;
-    double rho_ref; // populations are stored as f_i - w_i rho_ref (0 for FP64)
+    double rho_ref; // populations are stored as f_i - w_i rho_ref (0 for FP64 and the
+                    // per-cell mode)
+    size_t r_off;   // per-cell mode: byte offset of the FP32 reference block in a buffer
+    int r_pitch;    // per-cell mode: row pitch of that block, in floats
     double s_e, s_z, s_q; // MRT rates 1/tau_e, 1/tau_zeta, 1/tau_q (the stress rows use omega)
     int coll;       // lbm_collision
     int force_on;
@@ -148,11 +165,42 @@ __device__ __forceinline__ R ld(const E *__restrict__ row, uint32_t byte_off)
     return (R) * (const E *)((const char *)row + byte_off);
 }
 
-template <class E, class R>
+// The pulled values come back as deviations d_i = f_i - w_i ref from a
+// reference density ref: rho_ref for the shifted modes (0 for FP64), and in
+// the per-cell mode the cell's own reference R(x), so that every FP32
+// operation works on small deviations.
+template <int ST, class E = typename Store<ST>::E, class R = typename Store<ST>::R>
 __device__ __forceinline__ void load_pulled(const E *__restrict__ src, const Coeffs &c, int r,
-                                            const Cols &x, R d[kQ])
+                                            const Cols &x, R d[kQ], R &ref)
 {
     const int rm = wrap_lo(r - 1, c.ny), rp = wrap_hi(r + 1, c.ny);
+    if constexpr (Store<ST>::local) {
+        // f_i = X_i + w_i R at the sending cell x - c_i, so d_i = X_i +
+        // w_i (R(x - c_i) - R(x)).  R is FP32 and its column offsets are twice
+        // those of the binary16 populations.
+        const float *rb = (const float *)((const char *)src + c.r_off);
+        const float *q_r = rb + (size_t)r * c.r_pitch;
+        const float *q_m = rb + (size_t)rm * c.r_pitch;
+        const float *q_p = rb + (size_t)rp * c.r_pitch;
+        const Cols y{2 * x.o, 2 * x.m, 2 * x.p};
+        const R w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
+        const size_t P = c.plane;
+        const E *row_r = src + (size_t)r * c.pitch;
+        const E *row_m = src + (size_t)rm * c.pitch;
+        const E *row_p = src + (size_t)rp * c.pitch;
+        ref = ld<float, R>(q_r, y.o);
+        d[0] = ld<E, R>(row_r, x.o);
+        d[1] = fma(w1, ld<float, R>(q_r, y.m) - ref, ld<E, R>(row_r + 1 * P, x.m));
+        d[2] = fma(w1, ld<float, R>(q_m, y.o) - ref, ld<E, R>(row_m + 2 * P, x.o));
+        d[3] = fma(w1, ld<float, R>(q_r, y.p) - ref, ld<E, R>(row_r + 3 * P, x.p));
+        d[4] = fma(w1, ld<float, R>(q_p, y.o) - ref, ld<E, R>(row_p + 4 * P, x.o));
+        d[5] = fma(w2, ld<float, R>(q_m, y.m) - ref, ld<E, R>(row_m + 5 * P, x.m));
+        d[6] = fma(w2, ld<float, R>(q_m, y.p) - ref, ld<E, R>(row_m + 6 * P, x.p));
+        d[7] = fma(w2, ld<float, R>(q_p, y.p) - ref, ld<E, R>(row_p + 7 * P, x.p));
+        d[8] = fma(w2, ld<float, R>(q_p, y.m) - ref, ld<E, R>(row_p + 8 * P, x.m));
+        return;
+    }
+    ref = (R)c.rho_ref;
     const size_t P = c.plane;
     const E *row_r = src + (size_t)r * c.pitch;
     const E *row_m = src + (size_t)rm * c.pitch;
@@ -173,10 +221,9 @@ __device__ __forceinline__ void load_pulled(const E *__restrict__ src, const Coe
 // false when the density is outside the EOS domain (with FORCE = 0, when it
 // is not positive and finite).
 template <int FORCE, class R>
-__device__ __forceinline__ bool rho_psi(const R d[kQ], const Phys<R> &P, R &rho, R &psi)
+__device__ __forceinline__ bool rho_psi(const R d[kQ], R ref, const Phys<R> &P, R &rho, R &psi)
 {
-    rho = ((((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8]) +
-          P.rho_ref;
+    rho = ((((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8]) + ref;
     if (!FORCE) {
         psi = R(0);
         return rho > R(0) && rho < R(INFINITY);
@@ -244,7 +291,7 @@ __device__ __forceinline__ void velocity(const R d[kQ], R rho, R Fx, R Fy, R &ux
 // explicit fma(); the file is compiled without implicit contraction, so every
 // inlined copy rounds the same way.
 template <class R>
-__device__ __forceinline__ void collide(R d[kQ], R rho, R ux, R uy, R Fx, R Fy,
+__device__ __forceinline__ void collide(R d[kQ], R ref, R rho, R ux, R uy, R Fx, R Fy,
                                         const Phys<R> &P)
 {
     // omega (f^eq_i - w_i rho_ref) + S_i = w_i [A + c_i.B + (c_i.u)(h c_i.u + m c_i.F)]
@@ -254,7 +301,7 @@ __device__ __forceinline__ void collide(R d[kQ], R rho, R ux, R uy, R Fx, R Fy,
     const R orho = om * rho;
     const R usq = fma(ux, ux, uy * uy);
     const R uF = fma(ux, Fx, uy * Fy);
-    const R A = fma(om, fma(rho, R(-1.5) * usq, rho - P.rho_ref), R(-3) * g * uF);
+    const R A = fma(om, fma(rho, R(-1.5) * usq, rho - ref), R(-3) * g * uF);
     const R Bx = R(3) * fma(orho, ux, g * Fx), By = R(3) * fma(orho, uy, g * Fy);
     const R h = R(4.5) * orho;
     const R mx = R(9) * g * Fx, my = R(9) * g * Fy;
@@ -456,20 +503,21 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
     };
 
     R f[K][kQ];
+    R fref[K];  // reference density of each population set
     Row<R> rw[K];
 
     // prologue: psi of the trailing row (rw[0]) and the current row (rw[1]);
     // populations of segment rows 0 .. PF (clamped to nrows) into sets 0 .. PF
     {
-        R ft[kQ];
+        R ft[kQ], ftref;
         const int rt = lattice_row(-1);
-        load_pulled<E, R>(src, c, rt, cols, ft);
-        load_pulled<E, R>(src, c, y0, cols, f[0]);
+        load_pulled<ST>(src, c, rt, cols, ft, ftref);
+        load_pulled<ST>(src, c, y0, cols, f[0], fref[0]);
 #pragma unroll
         for (int p = 1; p <= PF; ++p)
-            load_pulled<E, R>(src, c, lattice_row(p < nrows ? p : nrows), cols, f[p]);
-        check(rho_psi<FORCE, R>(ft, P, rw[0].rho, rw[0].o), rt);
-        check(rho_psi<FORCE, R>(f[0], P, rw[1].rho, rw[1].o), y0);
+            load_pulled<ST>(src, c, lattice_row(p < nrows ? p : nrows), cols, f[p], fref[p]);
+        check(rho_psi<FORCE, R>(ft, ftref, P, rw[0].rho, rw[0].o), rt);
+        check(rho_psi<FORCE, R>(f[0], fref[0], P, rw[1].rho, rw[1].o), y0);
         lds[tx] = rw[0].o;
         lds[BX + tx] = rw[1].o;
         __syncthreads();
@@ -489,9 +537,10 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
         const int y = y0 + k * DIR;
         {
             const int kf = k + 1 + PF;
-            load_pulled<E, R>(src, c, lattice_row(kf < nrows ? kf : nrows), cols, f[fetch]);
+            load_pulled<ST>(src, c, lattice_row(kf < nrows ? kf : nrows), cols, f[fetch],
+                            fref[fetch]);
         }
-        check(rho_psi<FORCE, R>(f[lead], P, L.rho, L.o), lattice_row(k + 1));
+        check(rho_psi<FORCE, R>(f[lead], fref[lead], P, L.rho, L.o), lattice_row(k + 1));
         R *buf = lds + (k & 1) * BX;
         buf[tx] = L.o;
         __syncthreads();
@@ -510,13 +559,37 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
             if constexpr (COLL == LBM_COLL_MRT)
                 collide_mrt<R>(f[cur], C.rho, ux, uy, Fx, Fy, P);
             else
-                collide<R>(f[cur], C.rho, ux, uy, Fx, Fy, P);
+                collide<R>(f[cur], fref[cur], C.rho, ux, uy, Fx, Fy, P);
             if (interior) {
                 const size_t prow = (size_t)y * c.pitch;
+                if constexpr (Store<ST>::local) {
+                    // per-cell reference: the new R = sum_i f*_i = ref + s with
+                    // s = sum_i d*_i, X_i = round(f*_i - w_i R) = round(d*_i - w_i s),
+                    // then R corrected by the rounding errors so that the cell's
+                    // nine X_i + w_i R keep its mass
+                    const R *g = f[cur];
+                    const R sd =
+                        (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) +
+                        g[8];
+                    R err = R(0);
 #pragma unroll
-                for (int i = 0; i < kQ; ++i)
-                    __builtin_nontemporal_store(
-                        (E)f[cur][i], (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                    for (int i = 0; i < kQ; ++i) {
+                        const R w = i == 0 ? R(4.0 / 9.0) : (i < 5 ? R(1.0 / 9.0) : R(1.0 / 36.0));
+                        const R dev = fma(-w, sd, g[i]);
+                        const E X = (E)dev;
+                        err += dev - (R)X;
+                        __builtin_nontemporal_store(
+                            X, (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                    }
+                    float *rrow = (float *)((char *)dst + c.r_off) + (size_t)y * c.r_pitch;
+                    __builtin_nontemporal_store((float)(fref[cur] + (sd + err)),
+                                                (float *)((char *)rrow + 2 * cols.o));
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kQ; ++i)
+                        __builtin_nontemporal_store(
+                            (E)f[cur][i], (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                }
             }
         } else if (MODE == kMoments) {
             if (interior) {
@@ -697,34 +770,66 @@ __global__ __launch_bounds__(256) void reduce_partials(const double *__restrict_
     }
 }
 
-// Initial state f(0) = f^eq(rho0, u0) in pull storage: X_i(z) holds
-// f_i^eq at z + c_i, stored as the deviation from w_i rho_ref, rounded once.
+// The nine FP64 values v_i that cell (x, y) sends (v_i reaches x + c_i) into
+// pull storage: the deviation from w_i rho_ref rounded once, or in the
+// per-cell mode R = sum_i v_i, X_i = round(v_i - w_i R) and R corrected by
+// the rounding errors, rounded to FP32.
+template <int ST>
+__device__ __forceinline__ void store_cell(void *__restrict__ X_v, const Coeffs &c, int x, int y,
+                                           const double v[kQ])
+{
+    using E = typename Store<ST>::E;
+    E *X = (E *)X_v;
+    if constexpr (Store<ST>::local) {
+        double R = 0.0;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            R += v[i];
+        double err = 0.0;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const double dev = v[i] - weight(i) * R;
+            const E q = (E)dev;
+            err += dev - (double)q;
+            X[i * c.plane + (size_t)y * c.pitch + x] = q;
+        }
+        float *rb = (float *)((char *)X_v + c.r_off);
+        rb[(size_t)y * c.r_pitch + x] = (float)(R + err);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            X[i * c.plane + (size_t)y * c.pitch + x] = (E)(v[i] - weight(i) * c.rho_ref);
+    }
+}
+
+// Initial state f(0) = f^eq(rho0, u0) in pull storage: cell z sends f_i^eq at
+// z + c_i.
 template <int ST>
 __global__ __launch_bounds__(256) void init_kernel(void *__restrict__ X_v, Coeffs c,
                                                     const double *__restrict__ rho0,
                                                     const double *__restrict__ ux0,
                                                     const double *__restrict__ uy0)
 {
-    using E = typename Store<ST>::E;
-    E *X = (E *)X_v;
     const size_t n = (size_t)c.nx * c.ny;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int x = (int)(k % c.nx), y = (int)(k / c.nx);
     const int cx[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     const int cy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    double v[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         const int xx = wrap_hi(wrap_lo(x + cx[i], c.nx), c.nx);
         const int yy = wrap_hi(wrap_lo(y + cy[i], c.ny), c.ny);
         const size_t s = (size_t)yy * c.nx + xx;
-        const double feq = feq_dir(i, rho0[s], ux0 ? ux0[s] : 0.0, uy0 ? uy0[s] : 0.0);
-        X[i * c.plane + (size_t)y * c.pitch + x] = (E)(feq - weight(i) * c.rho_ref);
+        v[i] = feq_dir(i, rho0[s], ux0 ? ux0[s] : 0.0, uy0 ? uy0[s] : 0.0);
     }
+    store_cell<ST>(X_v, c, x, y, v);
 }
 
 // Canonical f(t) <-> pull storage.  to_canonical: f_i(x) = w_i rho_ref +
-// X_i(x - c_i); otherwise X_i(z) = round(f_i(z + c_i) - w_i rho_ref).
+// X_i(x - c_i) (w_i R(x - c_i) + X_i(x - c_i) in the per-cell mode);
+// otherwise cell z stores the values f_i(z + c_i) it sends (store_cell).
 // Canonical arrays are dense FP64 [9][ny][nx]; the storage has row pitch
 // c.pitch and plane stride c.plane.
 template <int ST>
@@ -739,23 +844,31 @@ __global__ __launch_bounds__(256) void permute_kernel(const void *__restrict__ i
     const int x = (int)(k % c.nx), y = (int)(k / c.nx);
     const int cx[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     const int cy[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    if (to_canonical) {
+        const E *in = (const E *)in_v;
+        double *out = (double *)out_v;
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const double base = weight(i) * c.rho_ref;
-        if (to_canonical) {
-            const E *in = (const E *)in_v;
-            double *out = (double *)out_v;
+        for (int i = 0; i < kQ; ++i) {
             const int xx = wrap_hi(wrap_lo(x - cx[i], c.nx), c.nx);
             const int yy = wrap_hi(wrap_lo(y - cy[i], c.ny), c.ny);
-            out[i * n + k] = base + (double)in[i * c.plane + (size_t)yy * c.pitch + xx];
-        } else {
-            const double *in = (const double *)in_v;
-            E *out = (E *)out_v;
+            const double X = (double)in[i * c.plane + (size_t)yy * c.pitch + xx];
+            if constexpr (Store<ST>::local) {
+                const float *rb = (const float *)((const char *)in_v + c.r_off);
+                out[i * n + k] = X + weight(i) * (double)rb[(size_t)yy * c.r_pitch + xx];
+            } else {
+                out[i * n + k] = weight(i) * c.rho_ref + X;
+            }
+        }
+    } else {
+        const double *in = (const double *)in_v;
+        double v[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
             const int xx = wrap_hi(wrap_lo(x + cx[i], c.nx), c.nx);
             const int yy = wrap_hi(wrap_lo(y + cy[i], c.ny), c.ny);
-            out[i * c.plane + (size_t)y * c.pitch + x] =
-                (E)(in[i * n + (size_t)yy * c.nx + xx] - base);
+            v[i] = in[i * n + (size_t)yy * c.nx + xx];
         }
+        store_cell<ST>(out_v, c, x, y, v);
     }
 }
 
@@ -812,13 +925,16 @@ constexpr int kGraphSteps = 8;
 
 struct Layout {
     size_t err, diag_out, partials, rho_snap, bufA, bufB, total, plane, pitch;
+    size_t r_off, r_pitch;  // per-cell mode: FP32 reference block after the populations
 };
 
 // Population storage, row-interleaved: row y of population i starts at
 // element y * pitch + i * plane with plane = nx rounded up to 128 bytes and
 // pitch = 9 plane.  Every row starts on a 128-byte boundary.  (On 2048 x 2048
 // FP64 a 9-population stream in the kernel's walk order measured 6.3 TB/s in
-// this layout against 6.0 TB/s with whole planes one after another.)
+// this layout against 6.0 TB/s with whole planes one after another.)  In the
+// per-cell mode each buffer continues with the FP32 reference densities R,
+// rows of nx rounded up to 128 bytes.
 Layout layout_for(const lbm_params *p)
 {
     Layout L;
@@ -835,10 +951,14 @@ Layout layout_for(const lbm_params *p)
     off += round_up((size_t)kMaxTiles * kDiag * sizeof(double), kAlign);
     L.rho_snap = off;
     off += round_up(n * sizeof(double), kAlign);
+    L.r_off = round_up(L.pitch * p->ny * es, kAlign);
+    L.r_pitch = round_up((size_t)p->nx, 32);
+    const size_t buf =
+        L.r_off + (p->storage == LBM_STORE_F16_LOCAL ? round_up(L.r_pitch * p->ny * 4, kAlign) : 0);
     L.bufA = off;
-    off += round_up(L.pitch * p->ny * es, kAlign);
+    off += buf;
     L.bufB = off;
-    off += round_up(L.pitch * p->ny * es, kAlign);
+    off += buf;
     L.total = off;
     return L;
 }
@@ -861,7 +981,7 @@ bool params_valid(const lbm_params *p, std::string *why)
     if (p->force_on != 0 && p->force_on != 1) return fail("force_on must be 0 or 1");
     if (p->m2_trace_alt != 0 && p->m2_trace_alt != 1) return fail("m2_trace_alt must be 0 or 1");
     if (p->storage != LBM_STORE_F64 && p->storage != LBM_STORE_F32_SHIFTED &&
-        p->storage != LBM_STORE_F16_SHIFTED)
+        p->storage != LBM_STORE_F16_SHIFTED && p->storage != LBM_STORE_F16_LOCAL)
         return fail("unknown storage mode");
     if (!std::isfinite(p->rho_ref)) return fail("rho_ref not finite");
     if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_MRT)
@@ -874,8 +994,9 @@ bool params_valid(const lbm_params *p, std::string *why)
     return true;
 }
 
-Coeffs make_coeffs(const lbm_params *p, size_t pitch, size_t plane)
+Coeffs make_coeffs(const lbm_params *p, const Layout &L)
 {
+    const size_t pitch = L.pitch, plane = L.plane;
     Coeffs c;
     c.nx = p->nx;
     c.ny = p->ny;
@@ -890,7 +1011,11 @@ Coeffs make_coeffs(const lbm_params *p, size_t pitch, size_t plane)
     c.cSC = -6.0 * p->G;
     c.cA = 9.0 * p->G * (1.5 * p->epsilon - p->sigma + 1.0);
     c.cB = 9.0 * p->G * (p->sigma - 1.0);
-    c.rho_ref = p->storage == LBM_STORE_F64 ? 0.0 : p->rho_ref;
+    c.rho_ref = (p->storage == LBM_STORE_F32_SHIFTED || p->storage == LBM_STORE_F16_SHIFTED)
+                    ? p->rho_ref
+                    : 0.0;
+    c.r_off = L.r_off;
+    c.r_pitch = (int)L.r_pitch;
     c.coll = p->collision;
     c.s_e = p->collision == LBM_COLL_MRT ? 1.0 / p->tau_e : 0.0;
     c.s_z = p->collision == LBM_COLL_MRT ? 1.0 / p->tau_zeta : 0.0;
@@ -902,7 +1027,7 @@ Coeffs make_coeffs(const lbm_params *p, size_t pitch, size_t plane)
 }
 
 // Strip width alignment in columns: 128 bytes of FP64, 64 bytes of FP32 or FP16.
-int strip_align(int storage) { return storage == LBM_STORE_F16_SHIFTED ? 32 : 16; }
+int strip_align(int storage) { return is_f16(storage) ? 32 : 16; }
 
 bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl,
                 long long limit = kMaxTiles)
@@ -946,7 +1071,7 @@ void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
     }
     Tiles tb;
     make_tiles(nx, ny, best, 1 << 30, align, &tb);
-    const double target_waves = 256.0 * (storage == LBM_STORE_F16_SHIFTED ? 20.0 : 64.0);
+    const double target_waves = 256.0 * (is_f16(storage) ? 20.0 : 64.0);
     int nseg = (int)std::ceil(target_waves / ((double)tb.nstrips * (best / 64)));
     nseg = std::max(1, std::min(nseg, ny));
     int rows = (ny + nseg - 1) / nseg;
@@ -1013,6 +1138,8 @@ hipError_t launch_sweep_f(lbm_handle *h, const void *src, void *dst, Fields fo)
         return launch_sweep_c<MODE, FORCE, LBM_STORE_F32_SHIFTED>(h, src, dst, fo);
     case LBM_STORE_F16_SHIFTED:
         return launch_sweep_c<MODE, FORCE, LBM_STORE_F16_SHIFTED>(h, src, dst, fo);
+    case LBM_STORE_F16_LOCAL:
+        return launch_sweep_c<MODE, FORCE, LBM_STORE_F16_LOCAL>(h, src, dst, fo);
     }
     return hipErrorInvalidValue;
 }
@@ -1036,8 +1163,12 @@ void launch_init(lbm_handle *h, unsigned blocks, const double *rho0, const doubl
         hipLaunchKernelGGL(init_kernel<LBM_STORE_F32_SHIFTED>, dim3(blocks), dim3(256), 0,
                            h->stream, h->cur, h->c, rho0, ux0, uy0);
         break;
-    default:
+    case LBM_STORE_F16_SHIFTED:
         hipLaunchKernelGGL(init_kernel<LBM_STORE_F16_SHIFTED>, dim3(blocks), dim3(256), 0,
+                           h->stream, h->cur, h->c, rho0, ux0, uy0);
+        break;
+    default:
+        hipLaunchKernelGGL(init_kernel<LBM_STORE_F16_LOCAL>, dim3(blocks), dim3(256), 0,
                            h->stream, h->cur, h->c, rho0, ux0, uy0);
         break;
     }
@@ -1056,8 +1187,12 @@ void launch_permute(lbm_handle *h, const void *in, void *out, int to_canonical)
         hipLaunchKernelGGL(permute_kernel<LBM_STORE_F32_SHIFTED>, grid, dim3(256), 0, h->stream,
                            in, out, h->c, to_canonical);
         break;
-    default:
+    case LBM_STORE_F16_SHIFTED:
         hipLaunchKernelGGL(permute_kernel<LBM_STORE_F16_SHIFTED>, grid, dim3(256), 0, h->stream,
+                           in, out, h->c, to_canonical);
+        break;
+    default:
+        hipLaunchKernelGGL(permute_kernel<LBM_STORE_F16_LOCAL>, grid, dim3(256), 0, h->stream,
                            in, out, h->c, to_canonical);
         break;
     }
@@ -1123,6 +1258,7 @@ hipError_t launch_batch_f(lbm_batch *b)
     case LBM_STORE_F64: return launch_batch_c<FORCE, LBM_STORE_F64>(b);
     case LBM_STORE_F32_SHIFTED: return launch_batch_c<FORCE, LBM_STORE_F32_SHIFTED>(b);
     case LBM_STORE_F16_SHIFTED: return launch_batch_c<FORCE, LBM_STORE_F16_SHIFTED>(b);
+    case LBM_STORE_F16_LOCAL: return launch_batch_c<FORCE, LBM_STORE_F16_LOCAL>(b);
     }
     return hipErrorInvalidValue;
 }
@@ -1278,7 +1414,7 @@ lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspac
     lbm_handle *h = new (std::nothrow) lbm_handle();
     if (!h) return LBM_ERR_OOM;
     h->p = *params;
-    h->c = make_coeffs(params, L.pitch, L.plane);
+    h->c = make_coeffs(params, L);
     h->stream = (hipStream_t)hip_stream;
     char *ws = (char *)d_workspace;
     h->err = (unsigned long long *)(ws + L.err);

@@ -21,7 +21,7 @@
 
 namespace {
 
-constexpr int kStorages = 3;
+constexpr int kStorages = 4;
 // one batch per (storage mode, force switch, collision operator)
 constexpr int kBatchKeys = kStorages * 2 * 2;
 

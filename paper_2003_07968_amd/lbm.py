@@ -27,6 +27,7 @@ LBM_ERR_STATE = -5
 LBM_STORE_F64 = 0
 LBM_STORE_F32_SHIFTED = 1
 LBM_STORE_F16_SHIFTED = 2
+LBM_STORE_F16_LOCAL = 3
 LBM_COLL_BGK = 0
 LBM_COLL_MRT = 1
 

@@ -62,7 +62,8 @@ def unit_cs_coexistence(tr: float):
     return UNIT_CS_MAXWELL[keys[-1]]
 
 
-STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+# f16l: binary16 deviations from w_i times a per-cell FP32 reference density
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "f16l": 3}
 
 
 COLLISION = {"bgk": 0, "mrt": 1}
@@ -98,8 +99,8 @@ def shift_reference(rho0, storage):
     two-phase field is stored as small deviations (binary16 keeps 11
     significant bits of each deviation; with the mean as reference the gas
     populations would be stored as deviations several times larger than
-    themselves).  FP64 storage takes no reference."""
-    if storage in ("f64", 0):
+    themselves).  FP64 storage and the per-cell mode take no global reference."""
+    if storage in ("f64", 0, "f16l", 3):
         return 0.0
     if storage in ("f32", 1):
         return float(np.mean(rho0))

@@ -28,7 +28,7 @@ def _mixed(storage="f64", count=6, seed=3):
     return W.batch_case(count=count, seed=seed, storage=storage, side_range=(24, 160))
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "f16l"])
 def test_batch_equals_alone(storage):
     # eager steps (3), then graph replays (8-step graphs) with checks and
     # eager work in between, then a remainder: every lattice bitwise equal to

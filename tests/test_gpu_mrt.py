@@ -94,7 +94,7 @@ def test_equal_rates_give_the_bgk_result():
     assert float((fa - fb).abs().max() / fa.abs().max()) < 1e-13
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16l"])
 def test_mrt_reduced_storage_matches_emulating_oracle(oracle, storage):
     require_gpu()
     p, rho0 = W.droplet_64(seed=1)

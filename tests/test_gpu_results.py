@@ -17,7 +17,7 @@ The FP64 results come from the FP64 GPU path, which matches the CPU oracle
 to 1e-12 per field (test_gpu_parity.py); running these sizes and horizons on
 the oracle would take hours.  The measured errors are logged.
 
-FP16 storage with one reference density for the whole lattice does not
+FP16 storage with one reference density for the whole lattice (f16) does not
 reproduce the oscillation: collision increments smaller than half a binary16
 ulp of the liquid's stored deviations are lost, the droplet's shape drifts by
 many cells and the period comes out several percent to tens of percent off
@@ -25,7 +25,9 @@ many cells and the period comes out several percent to tens of percent off
 its mass drift and Laplace errors are asserted at the measured level.  The
 FP16 numbers are a property of the format with a global shift, not of the
 kernel: test_gpu_storage.py shows the kernel agreeing with the FP64 oracle
-run with the same binary16 rounding."""
+run with the same binary16 rounding.  FP16 storage with a per-cell FP32
+reference density (f16l) keeps the deviations small in both phases and tracks
+FP64 closely; its errors are asserted like FP32's."""
 import numpy as np
 import pytest
 import torch
@@ -77,11 +79,14 @@ def _oscillation(tau, storage):
 # extent: lattice units, max over the time series; drift: |dM|/M at 40000
 # steps), a few times the measured worst case over tau in {0.6, 0.8, 1.0}:
 #   FP32: period 4.3e-4, extent 0.041 cells, drift 2.2e-4 (tau = 0.6);
-#   FP16: drift 2.0e-2 (period and extent not asserted, see above);
+#   FP16 with one global reference: drift 2.0e-2 (period and extent not
+#   asserted, see above);
+#   FP16 with a per-cell FP32 reference (f16l): period 1.25e-2 (tau = 1),
+#   extent 0.69 cells, drift 4.5e-7;
 #   FP64: drift 2.9e-12 (mass is conserved to rounding).
-PERIOD_TOL = {"f32": 2e-3}
-EXTENT_TOL = {"f32": 0.2}
-DRIFT_TOL = {"f64": 1e-11, "f32": 1e-3, "f16": 5e-2}
+PERIOD_TOL = {"f32": 2e-3, "f16l": 4e-2}
+EXTENT_TOL = {"f32": 0.2, "f16l": 2.0}
+DRIFT_TOL = {"f64": 1e-11, "f32": 1e-3, "f16": 5e-2, "f16l": 5e-6}
 
 
 @pytest.mark.parametrize("tau", [0.6, 0.8, 1.0])
@@ -95,7 +100,7 @@ def test_oscillation_period_and_mass_drift(tau):
     log(f"tau={tau}: f64 period {ref['T']:.1f} (Lamb {Ta:.1f}, {ref['T'] / Ta - 1:+.3f}), "
         f"mass drift {ref['drift']:.2e}")
     assert ref["drift"] <= DRIFT_TOL["f64"]
-    for st in ("f32", "f16"):
+    for st in ("f32", "f16", "f16l"):
         res = _oscillation(tau, st)
         e_T = abs(res["T"] / ref["T"] - 1)
         e_r = float(np.abs(res["r"] - ref["r"]).max())
@@ -109,9 +114,9 @@ def test_oscillation_period_and_mass_drift(tau):
 
 LAPLACE_RADII = (16.0, 22.0, 28.0, 34.0)
 # relative errors against FP64; measured: FP32 1.2e-4 per radius and 2.7e-6 on
-# the fitted slope, FP16 0.13 and 0.099
-DP_TOL = {"f32": 1e-3, "f16": 0.3}
-GAMMA_TOL = {"f32": 1e-4, "f16": 0.2}
+# the fitted slope, FP16 0.13 and 0.099, f16l 1.4e-3 and 1.5e-4
+DP_TOL = {"f32": 1e-3, "f16": 0.3, "f16l": 5e-3}
+GAMMA_TOL = {"f32": 1e-4, "f16": 0.2, "f16l": 1e-3}
 
 
 def _laplace(storage, n=128, tr=0.8, steps=16000):
@@ -140,7 +145,7 @@ def test_laplace_pressure_vs_fp64():
     T = 0.8 * W.UNIT_CS_TC
     g_pi = A.planar_surface_tension_quad(A.UNIT_EOS, T, 1.73, 1.0)
     log(f"f64: R {np.round(R64, 2)}, dP {dP64}, gamma {g64:.5f} (planar {g_pi:.5f})")
-    for st in ("f32", "f16"):
+    for st in ("f32", "f16", "f16l"):
         R, dP, g = _laplace(st)
         e_dp = float(np.max(np.abs(dP / dP64 - 1)))
         e_g = abs(g / g64 - 1)

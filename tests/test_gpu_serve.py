@@ -17,10 +17,10 @@ pytestmark = pytest.mark.gpu
 
 # the server keeps one batch (and its table in the arena) per storage mode,
 # force switch and collision operator
-BATCH_KEYS = 3 * 2 * 2
+BATCH_KEYS = 4 * 2 * 2
 
 
-def _jobs(count, seed, storages=("f64", "f32", "f16"), sides=(24, 96), steps=(0, 150)):
+def _jobs(count, seed, storages=("f64", "f32", "f16", "f16l"), sides=(24, 96), steps=(0, 150)):
     """Seeded mixed jobs: droplet or slab, random T_r, sigma, tau, storage."""
     rng = np.random.default_rng(seed)
     out = []

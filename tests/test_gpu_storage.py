@@ -1,5 +1,6 @@
 """Reduced-precision storage (populations kept as FP32 or FP16 deviations
-from w_i rho_ref, FP32 arithmetic) against the CPU oracle.
+from w_i rho_ref, or as FP16 deviations from w_i times a per-cell FP32
+reference density; FP32 arithmetic) against the CPU oracle.
 
 Two comparisons, each with its stated tolerance:
   * against the oracle run with the same storage rounding (FP64 arithmetic,
@@ -24,10 +25,14 @@ pytestmark = pytest.mark.gpu
 # storage-emulating oracle after 100 steps of the 64 x 64 droplet.  FP32: the
 # arithmetic differs by a few float ulps per step (~1e-7 relative); FP16: a
 # flipped binary16 rounding of a deviation is 2^-11 of its size.
-EMULATED_TOL = {"f32": 2e-5, "f16": 2e-3}
+# f16l (binary16 deviations from a per-cell FP32 reference): a flipped
+# rounding is 2^-11 of a deviation that is at most ~1e-2 of f (at interfaces),
+# some 35 times less than with the global reference; measured 9.5e-5 after
+# 100 steps of the MRT droplet.
+EMULATED_TOL = {"f32": 2e-5, "f16": 2e-3, "f16l": 5e-4}
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16l"])
 def test_matches_storage_emulating_oracle(oracle, storage):
     require_gpu()
     p, rho0 = W.droplet_64(seed=1)
@@ -47,7 +52,7 @@ def test_matches_storage_emulating_oracle(oracle, storage):
     lat.sync()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16l"])
 def test_initial_state_is_rounded_equilibrium(oracle, storage):
     require_gpu()
     p, rho0 = W.droplet_64(seed=2)
@@ -60,7 +65,7 @@ def test_initial_state_is_rounded_equilibrium(oracle, storage):
     assert np.array_equal(g, f) or np.abs(g - f).max() <= 4 * np.finfo(float).eps
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16l"])
 def test_launch_shapes_bitwise_identical(storage):
     require_gpu()
     p = W.params(301, 203, tr=0.8, storage=storage)
@@ -81,11 +86,13 @@ def test_launch_shapes_bitwise_identical(storage):
 # lost, and not symmetrically, so the mass drifts by about 1 % per 2000
 # steps on this two-phase slab (the FP64-arithmetic oracle with the same
 # storage rounding drifts alike).  The coexistence densities stay close.
-MASS_DRIFT_TOL = {"f32": 1e-5, "f16": 3e-2}            # |dM|/M after 2000 steps
-COEX_TOL = {"f32": (1e-5, 5e-5), "f16": (2e-3, 1e-2)}  # (liquid, gas) relative, 8000 steps
+# f16l (per-cell FP32 reference) measured: drift 1.2e-7, liquid 1.7e-5, gas 1.1e-4.
+MASS_DRIFT_TOL = {"f32": 1e-5, "f16": 3e-2, "f16l": 1e-6}   # |dM|/M after 2000 steps
+COEX_TOL = {"f32": (1e-5, 5e-5), "f16": (2e-3, 1e-2),       # (liquid, gas) relative,
+            "f16l": (1e-4, 5e-4)}                           # 8000 steps
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16l"])
 def test_mass_drift_and_coexistence_vs_fp64(oracle, storage):
     # 128 x 4 slab (the flat interface is one-dimensional), T_r = 0.8, 8000
     # steps: bulk densities against the FP64 oracle run of the same input,
@@ -113,7 +120,7 @@ def test_mass_drift_and_coexistence_vs_fp64(oracle, storage):
     lat.sync()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16l"])
 def test_checkpoint_roundtrip(storage):
     require_gpu()
     p, rho0 = W.droplet_64(seed=5)
@@ -124,7 +131,19 @@ def test_checkpoint_roundtrip(storage):
     f = a.populations()
     b = gpu_lattice(p, rho0)
     b.set_populations(f, 30)
-    assert torch.equal(b.populations(), f)
+    if storage != "f16l":
+        assert torch.equal(b.populations(), f)
+        a.step(10)
+        b.step(10)
+        assert torch.equal(a.populations(), b.populations())
+        return
+    # per-cell reference: re-encoding moves each value by about one binary16
+    # rounding of its deviation (2^-11 of at most ~1e-2 of f) plus w_i times
+    # the cell's nine rounding errors, so a restart is close, not bitwise
+    # (measured 6.5e-6 after re-encoding, 2.5e-5 ten steps later)
+    e0 = float((b.populations() - f).abs().max() / f.abs().max())
     a.step(10)
     b.step(10)
-    assert torch.equal(a.populations(), b.populations())
+    e1 = float((b.populations() - a.populations()).abs().max() / f.abs().max())
+    log(f"  f16l restart: {e0:.2e} after re-encoding, {e1:.2e} ten steps later")
+    assert e0 <= 3e-5 and e1 <= 1e-4
