@@ -165,42 +165,14 @@ __device__ __forceinline__ R ld(const E *__restrict__ row, uint32_t byte_off)
     return (R) * (const E *)((const char *)row + byte_off);
 }
 
-// The pulled values come back as deviations d_i = f_i - w_i ref from a
-// reference density ref: rho_ref for the shifted modes (0 for FP64), and in
-// the per-cell mode the cell's own reference R(x), so that every FP32
-// operation works on small deviations.
+// The stored values X_i of the pulled populations, as R.  For the shifted
+// modes they are the deviations d_i = f_i - w_i rho_ref (rho_ref = 0 for
+// FP64); the per-cell mode turns them into deviations with reconstruct().
 template <int ST, class E = typename Store<ST>::E, class R = typename Store<ST>::R>
 __device__ __forceinline__ void load_pulled(const E *__restrict__ src, const Coeffs &c, int r,
-                                            const Cols &x, R d[kQ], R &ref)
+                                            const Cols &x, R d[kQ])
 {
     const int rm = wrap_lo(r - 1, c.ny), rp = wrap_hi(r + 1, c.ny);
-    if constexpr (Store<ST>::local) {
-        // f_i = X_i + w_i R at the sending cell x - c_i, so d_i = X_i +
-        // w_i (R(x - c_i) - R(x)).  R is FP32 and its column offsets are twice
-        // those of the binary16 populations.
-        const float *rb = (const float *)((const char *)src + c.r_off);
-        const float *q_r = rb + (size_t)r * c.r_pitch;
-        const float *q_m = rb + (size_t)rm * c.r_pitch;
-        const float *q_p = rb + (size_t)rp * c.r_pitch;
-        const Cols y{2 * x.o, 2 * x.m, 2 * x.p};
-        const R w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
-        const size_t P = c.plane;
-        const E *row_r = src + (size_t)r * c.pitch;
-        const E *row_m = src + (size_t)rm * c.pitch;
-        const E *row_p = src + (size_t)rp * c.pitch;
-        ref = ld<float, R>(q_r, y.o);
-        d[0] = ld<E, R>(row_r, x.o);
-        d[1] = fma(w1, ld<float, R>(q_r, y.m) - ref, ld<E, R>(row_r + 1 * P, x.m));
-        d[2] = fma(w1, ld<float, R>(q_m, y.o) - ref, ld<E, R>(row_m + 2 * P, x.o));
-        d[3] = fma(w1, ld<float, R>(q_r, y.p) - ref, ld<E, R>(row_r + 3 * P, x.p));
-        d[4] = fma(w1, ld<float, R>(q_p, y.o) - ref, ld<E, R>(row_p + 4 * P, x.o));
-        d[5] = fma(w2, ld<float, R>(q_m, y.m) - ref, ld<E, R>(row_m + 5 * P, x.m));
-        d[6] = fma(w2, ld<float, R>(q_m, y.p) - ref, ld<E, R>(row_m + 6 * P, x.p));
-        d[7] = fma(w2, ld<float, R>(q_p, y.p) - ref, ld<E, R>(row_p + 7 * P, x.p));
-        d[8] = fma(w2, ld<float, R>(q_p, y.m) - ref, ld<E, R>(row_p + 8 * P, x.m));
-        return;
-    }
-    ref = (R)c.rho_ref;
     const size_t P = c.plane;
     const E *row_r = src + (size_t)r * c.pitch;
     const E *row_m = src + (size_t)rm * c.pitch;
@@ -215,6 +187,59 @@ __device__ __forceinline__ void load_pulled(const E *__restrict__ src, const Coe
     d[7] = ld<E, R>(row_p + 7 * P, x.p);
     d[8] = ld<E, R>(row_p + 8 * P, x.m);
 }
+
+// R at columns x - 1, x, x + 1 of one lattice row.
+template <class R>
+struct Tri {
+    R l, o, r;
+};
+
+// Per-cell mode: the FP32 reference R of lattice row r at column x, and at
+// x - 1 for the first lane of the workgroup (its left neighbour is in no lane)
+// or x + 1 for every other lane (columns of R are twice as wide as those of
+// the binary16 populations).
+template <class R>
+struct RefPair {
+    R own, side;
+};
+
+template <class R>
+__device__ __forceinline__ RefPair<R> load_ref(const void *__restrict__ src, const Coeffs &c,
+                                               int r, const Cols &x, bool first)
+{
+    const float *row = (const float *)((const char *)src + c.r_off) + (size_t)r * c.r_pitch;
+    return RefPair<R>{ld<float, R>(row, 2 * x.o), ld<float, R>(row, 2 * (first ? x.m : x.p))};
+}
+
+// Per-cell mode: f_i = X_i + w_i R at the sending cell x - c_i, turned into
+// deviations from the cell's own reference, d_i = X_i + w_i (R(x - c_i) - R(x)),
+// so that every FP32 operation works on small numbers.  D, C, U hold R of the
+// lattice rows r - 1, r, r + 1.
+template <class R>
+__device__ __forceinline__ void reconstruct(R d[kQ], const Tri<R> &D, const Tri<R> &C,
+                                            const Tri<R> &U)
+{
+    const R w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0), ref = C.o;
+    d[1] = fma(w1, C.l - ref, d[1]);
+    d[2] = fma(w1, D.o - ref, d[2]);
+    d[3] = fma(w1, C.r - ref, d[3]);
+    d[4] = fma(w1, U.o - ref, d[4]);
+    d[5] = fma(w2, D.l - ref, d[5]);
+    d[6] = fma(w2, D.r - ref, d[6]);
+    d[7] = fma(w2, U.r - ref, d[7]);
+    d[8] = fma(w2, U.l - ref, d[8]);
+}
+
+// Reciprocal and square root in the arithmetic type: IEEE-rounded in FP64 (the
+// reference path); the hardware's single-instruction forms in FP32, whose
+// error of about one ulp is far below the storage rounding of the
+// reduced-precision modes.
+__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+__device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+__device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double root(double v) { return sqrt(v); }
+__device__ __forceinline__ float root(float v) { return __builtin_amdgcn_sqrtf(v); }
 
 // Density (Eq. FD) and pseudopotential (Eqs. CSEOS, DED) from the stored
 // deviations d_i = f_i - w_i rho_ref: rho = rho_ref + sum_i d_i.  Returns
@@ -231,9 +256,9 @@ __device__ __forceinline__ bool rho_psi(const R d[kQ], R ref, const Phys<R> &P, 
     const R br = P.eos_b * rho;
     const R num = fma(br, fma(br, R(1) - br, R(1)), R(1));  // 1 + br + br^2 - br^3
     const R om = R(1) - br;
-    const R pr = fma(P.kcT * rho, num / (om * om * om), -P.ka * rho * rho);
+    const R pr = fma(P.kcT * rho, quot(num, om * om * om), -P.ka * rho * rho);
     const R rad = fma(rho, R(-1.0 / 3.0), pr) * P.invG;
-    psi = sqrt(rad);
+    psi = root(rad);
     return rho > R(0) && br < R(1) && rad >= R(0) && rad < R(INFINITY);
 }
 
@@ -276,7 +301,7 @@ __device__ __forceinline__ void velocity(const R d[kQ], R rho, R Fx, R Fy, R &ux
 {
     const R jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]);
     const R jy = ((d[2] - d[4]) + (d[5] + d[6])) - (d[7] + d[8]);
-    const R inv = R(1) / rho;
+    const R inv = recip(rho);
     ux = (jx + R(0.5) * Fx) * inv;
     uy = (jy + R(0.5) * Fy) * inv;
 }
@@ -477,16 +502,24 @@ __device__ __forceinline__ void unroll(F &&f, std::integer_sequence<int, J...>)
 // around the loads the compiler's wait counters stay exact, so a prefetch
 // really stays in flight while the current row is computed.  Domain
 // failures are folded into a per-lane minimum key and published once.
+//
+// Per-cell mode: the reference R of each lattice row is loaded once (with one
+// side neighbour), one row ahead of the populations that need it, and the
+// other neighbour comes through a second double-buffered LDS row (a second
+// barrier per row).  The triples of R of the segment rows k, k + 1, k + 2
+// rotate with the population sets; the lead row k + 1 is reconstructed from
+// them when it is turned into psi.
 template <int BX, int MODE, int DIR, int PF, int FORCE, int ST, int COLL>
 __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ src,
                                      typename Store<ST>::E *__restrict__ dst, const Coeffs &c,
                                      long long t, const Fields &fo, double *__restrict__ rho_snap,
                                      int ys, int ye, int x, const Cols &cols, bool active,
-                                     bool interior, typename Store<ST>::R *lds,
+                                     bool interior, typename Store<ST>::R *lds, float *ldsr,
                                      double acc[kDiag], unsigned long long &bad)
 {
     using E = typename Store<ST>::E;
     using R = typename Store<ST>::R;
+    constexpr bool LOC = Store<ST>::local;
     constexpr int K = PF + 2;
     const Phys<R> P(c);
     const int tx = threadIdx.x;
@@ -503,21 +536,59 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
     };
 
     R f[K][kQ];
-    R fref[K];  // reference density of each population set
     Row<R> rw[K];
+    // per-cell mode: raw R of segment rows (slot = row mod K) and the triples
+    RefPair<R> rl[K];
+    Tri<R> tr[K];
+    const R gref = (R)c.rho_ref;  // the shifted modes' reference density
+    const bool first = tx == 0;
+    // the left neighbour of every lane but the first comes from the lane on
+    // its left; the right neighbour was loaded (the first lane takes it from
+    // lane 1)
+    auto tri_of = [&](const RefPair<R> &v, float *buf) {
+        buf[tx] = (float)v.own;
+        __syncthreads();
+        return first ? Tri<R>{v.side, v.own, (R)buf[1]} : Tri<R>{(R)buf[txm], v.own, v.side};
+    };
+    // lattice rows r - 1 and r + 1 of segment row k are segment rows k - DIR and k + DIR
+    auto rebuild = [&](R d[kQ], const Tri<R> &prev, const Tri<R> &here, const Tri<R> &next) {
+        if (DIR > 0)
+            reconstruct<R>(d, prev, here, next);
+        else
+            reconstruct<R>(d, next, here, prev);
+    };
 
     // prologue: psi of the trailing row (rw[0]) and the current row (rw[1]);
-    // populations of segment rows 0 .. PF (clamped to nrows) into sets 0 .. PF
+    // populations of segment rows 0 .. PF (clamped to nrows) into sets 0 .. PF;
+    // per-cell mode: R of segment rows -2 .. PF + 1 (clamped to nrows + 1)
     {
-        R ft[kQ], ftref;
+        R ft[kQ];
         const int rt = lattice_row(-1);
-        load_pulled<ST>(src, c, rt, cols, ft, ftref);
-        load_pulled<ST>(src, c, y0, cols, f[0], fref[0]);
+        load_pulled<ST>(src, c, rt, cols, ft);
+        load_pulled<ST>(src, c, y0, cols, f[0]);
 #pragma unroll
         for (int p = 1; p <= PF; ++p)
-            load_pulled<ST>(src, c, lattice_row(p < nrows ? p : nrows), cols, f[p], fref[p]);
-        check(rho_psi<FORCE, R>(ft, ftref, P, rw[0].rho, rw[0].o), rt);
-        check(rho_psi<FORCE, R>(f[0], fref[0], P, rw[1].rho, rw[1].o), y0);
+            load_pulled<ST>(src, c, lattice_row(p < nrows ? p : nrows), cols, f[p]);
+        R reft = gref, ref0 = gref;
+        if constexpr (LOC) {
+            const RefPair<R> rm2 = load_ref<R>(src, c, lattice_row(-2), cols, first);
+            const RefPair<R> rm1 = load_ref<R>(src, c, rt, cols, first);
+#pragma unroll
+            for (int p = 0; p <= PF + 1; ++p)
+                rl[p % K] = load_ref<R>(src, c, lattice_row(p < nrows + 1 ? p : nrows + 1), cols,
+                                        first);
+            const Tri<R> tm2 = tri_of(rm2, ldsr);
+            const Tri<R> tm1 = tri_of(rm1, ldsr + BX);
+            tr[0] = tri_of(rl[0], ldsr + 2 * BX);
+            tr[1 % K] = tri_of(rl[1 % K], ldsr + 3 * BX);
+            rebuild(ft, tm2, tm1, tr[0]);
+            rebuild(f[0], tm1, tr[0], tr[1 % K]);
+            reft = tm1.o;
+            ref0 = tr[0].o;
+            __syncthreads();  // ldsr is rewritten by the first row
+        }
+        check(rho_psi<FORCE, R>(ft, reft, P, rw[0].rho, rw[0].o), rt);
+        check(rho_psi<FORCE, R>(f[0], ref0, P, rw[1].rho, rw[1].o), y0);
         lds[tx] = rw[0].o;
         lds[BX + tx] = rw[1].o;
         __syncthreads();
@@ -537,10 +608,22 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
         const int y = y0 + k * DIR;
         {
             const int kf = k + 1 + PF;
-            load_pulled<ST>(src, c, lattice_row(kf < nrows ? kf : nrows), cols, f[fetch],
-                            fref[fetch]);
+            load_pulled<ST>(src, c, lattice_row(kf < nrows ? kf : nrows), cols, f[fetch]);
         }
-        check(rho_psi<FORCE, R>(f[lead], fref[lead], P, L.rho, L.o), lattice_row(k + 1));
+        R ref_cur = gref, ref_lead = gref;
+        if constexpr (LOC) {
+            // R of segment row k + 2 + PF into slot J (row k is done with it);
+            // the triple of row k + 2 completes the lead row k + 1
+            const int kr = k + 2 + PF;
+            const RefPair<R> nr =
+                load_ref<R>(src, c, lattice_row(kr < nrows + 1 ? kr : nrows + 1), cols, first);
+            tr[(J + 2) % K] = tri_of(rl[(J + 2) % K], ldsr + (k & 1) * BX);
+            rl[J % K] = nr;
+            rebuild(f[lead], tr[J % K], tr[(J + 1) % K], tr[(J + 2) % K]);
+            ref_cur = tr[J % K].o;
+            ref_lead = tr[(J + 1) % K].o;
+        }
+        check(rho_psi<FORCE, R>(f[lead], ref_lead, P, L.rho, L.o), lattice_row(k + 1));
         R *buf = lds + (k & 1) * BX;
         buf[tx] = L.o;
         __syncthreads();
@@ -559,7 +642,7 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
             if constexpr (COLL == LBM_COLL_MRT)
                 collide_mrt<R>(f[cur], C.rho, ux, uy, Fx, Fy, P);
             else
-                collide<R>(f[cur], fref[cur], C.rho, ux, uy, Fx, Fy, P);
+                collide<R>(f[cur], ref_cur, C.rho, ux, uy, Fx, Fy, P);
             if (interior) {
                 const size_t prow = (size_t)y * c.pitch;
                 if constexpr (Store<ST>::local) {
@@ -582,7 +665,7 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
                             X, (E *)((char *)(dst + i * c.plane + prow) + cols.o));
                     }
                     float *rrow = (float *)((char *)dst + c.r_off) + (size_t)y * c.r_pitch;
-                    __builtin_nontemporal_store((float)(fref[cur] + (sd + err)),
+                    __builtin_nontemporal_store((float)(ref_cur + (sd + err)),
                                                 (float *)((char *)rrow + 2 * cols.o));
                 } else {
 #pragma unroll
@@ -639,6 +722,7 @@ __device__ __forceinline__ void sweep_tile(const void *__restrict__ src_v, void 
     const E *src = (const E *)src_v;
     E *dst = (E *)dst_v;
     __shared__ R lds[2 * BX];
+    __shared__ float ldsr[Store<ST>::local ? 4 * BX : 1];
     const int seg = tile / tl.nstrips;
     const int strip = tile - seg * tl.nstrips;
     const int xs = strip * tl.width;
@@ -660,10 +744,10 @@ __device__ __forceinline__ void sweep_tile(const void *__restrict__ src_v, void 
     unsigned long long bad = ~0ull;
     if (seg & 1)
         walk<BX, MODE, -1, PF, FORCE, ST, COLL>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
-                                          interior, lds, acc, bad);
+                                          interior, lds, ldsr, acc, bad);
     else
         walk<BX, MODE, +1, PF, FORCE, ST, COLL>(src, dst, c, t, fo, rho_snap, ys, ye, x, cols, active,
-                                          interior, lds, acc, bad);
+                                          interior, lds, ldsr, acc, bad);
     if (bad != ~0ull) atomicMin(err, bad);
 
     if (MODE == kDiagnostics) {
@@ -694,9 +778,16 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return xcd * base + min(xcd, rem) + j;
 }
 
+// Waves per SIMD the compiler must leave room for: the per-cell mode with the
+// BGK collision holds one register more than four waves allow without the
+// bound (with it, 128 and no spills; the MRT variant would spill, so it runs
+// at three waves).
+template <int ST, int COLL>
+constexpr int kMinWaves = (Store<ST>::local && COLL == LBM_COLL_BGK) ? 4 : 1;
+
 // One sweep over one lattice.
 template <int BX, int MODE, int PF, int FORCE, int ST, int COLL>
-__global__ __launch_bounds__(BX) void sweep_kernel(const void *__restrict__ src,
+__global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void sweep_kernel(const void *__restrict__ src,
                                                    void *__restrict__ dst, Coeffs c, Tiles tl,
                                                    long long t,
                                                    unsigned long long *__restrict__ err,
@@ -723,7 +814,7 @@ struct BatchEntry {
 // is read from d_steps (so that a captured graph replays correctly); its
 // parity selects the source buffer.
 template <int BX, int PF, int FORCE, int ST, int COLL>
-__global__ __launch_bounds__(BX) void batch_step_kernel(const BatchEntry *__restrict__ table,
+__global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(const BatchEntry *__restrict__ table,
                                                         int nlat,
                                                         const long long *__restrict__ d_steps)
 {
@@ -1047,13 +1138,14 @@ bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl,
 
 // Default launch shape: 256-thread workgroups unless another width wastes
 // clearly fewer lanes on ragged strips (small lattices), then row segments
-// short enough for about 64 waves per CU on 256 CUs (20 for FP16 storage),
-// each segment at least 8 rows (FP64) or 5 rows (FP32, FP16).  Many short
-// segments keep more rows of loads in flight per CU (each segment starts with
-// a burst of three row loads); their halo rows come back mostly from cache.
+// short enough for about 64 waves per CU on 256 CUs (20 for FP16 storage, 28
+// for FP16 with the per-cell reference), each segment at least 8 rows (FP64)
+// or 5 rows (the others).  Many short segments keep more rows of loads in
+// flight per CU (each segment starts with a burst of three row loads); their
+// halo rows come back mostly from cache.
 // Measured on 2048 x 2048 in sweeps over 128..512 threads and 3..25 rows:
 // FP64 is fastest at (256 threads, 8 rows), FP32 at (256, 5..8), FP16 at
-// (256, 17).
+// (256, 16), FP16 with the per-cell reference at (256, 8..12).
 void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
 {
     int best = 256;
@@ -1071,7 +1163,8 @@ void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
     }
     Tiles tb;
     make_tiles(nx, ny, best, 1 << 30, align, &tb);
-    const double target_waves = 256.0 * (is_f16(storage) ? 20.0 : 64.0);
+    const double target_waves =
+        256.0 * (storage == LBM_STORE_F16_SHIFTED ? 20.0 : (storage == LBM_STORE_F16_LOCAL ? 28.0 : 64.0));
     int nseg = (int)std::ceil(target_waves / ((double)tb.nstrips * (best / 64)));
     nseg = std::max(1, std::min(nseg, ny));
     int rows = (ny + nseg - 1) / nseg;

@@ -113,10 +113,10 @@ def test_oscillation_period_and_mass_drift(tau):
 
 
 LAPLACE_RADII = (16.0, 22.0, 28.0, 34.0)
-# relative errors against FP64; measured: FP32 1.2e-4 per radius and 2.7e-6 on
-# the fitted slope, FP16 0.13 and 0.099, f16l 1.4e-3 and 1.5e-4
+# relative errors against FP64; measured: FP32 1.4e-4 per radius and 1.6e-5 on
+# the fitted slope, FP16 0.14 and 0.16, f16l 1.3e-3 and 5.6e-4
 DP_TOL = {"f32": 1e-3, "f16": 0.3, "f16l": 5e-3}
-GAMMA_TOL = {"f32": 1e-4, "f16": 0.2, "f16l": 1e-3}
+GAMMA_TOL = {"f32": 1e-4, "f16": 0.3, "f16l": 2e-3}
 
 
 def _laplace(storage, n=128, tr=0.8, steps=16000):
