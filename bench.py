@@ -175,7 +175,10 @@ def run_batch(args):
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": f"f32 arithmetic, {storage}-shifted storage", "data": "synthetic",
+        "dtype": {"f32": "f32 arithmetic, f32-shifted storage",
+                  "f16": "f32 arithmetic, f16-shifted storage",
+                  "f16l": "f32 arithmetic, f16 storage with per-cell f32 reference"}[storage],
+        "data": "synthetic",
         "config": {
             "workload": "batch of 256 D2Q9 droplet lattices, sides log-uniform [64, 512], "
                         "T_r U[0.55,0.95], sigma U[1/8,4], R0 U[0.15,0.35] side, seed 6; "
@@ -211,6 +214,7 @@ def serve_stream(jobs, arrivals, storage, arena_bytes, quantum):
     server's counters."""
     import numpy as np
     from paper_2003_07968_amd import lbm
+    from paper_2003_07968_amd import workloads as W
     srv = lbm.Server(arena_bytes=arena_bytes, max_resident=128, quantum=quantum, max_bypass=16)
     order = np.argsort(arrivals, kind="stable")
     done_at, ids = {}, {}
@@ -222,7 +226,8 @@ def serve_stream(jobs, arrivals, storage, arena_bytes, quantum):
             k = int(order[nxt])
             p, rho0, n = jobs[k]
             q = dict(p)
-            q["storage"] = {"f32": 1, "f16": 2}[storage]
+            q["storage"] = W.STORAGE[storage]
+            q["rho_ref"] = W.shift_reference(rho0, storage)
             ids[srv.submit(q, rho0, n)] = k
             nxt += 1
         st = srv.stats()
@@ -267,7 +272,7 @@ def run_serve(args):
         f"-> arrival rate {rate:.2f} jobs/s")
 
     served = {}
-    for storage in ("f32", "f16"):
+    for storage in ("f32", "f16", "f16l"):
         ttr, span, st = serve_stream(jobs, arrivals, storage, arena, quantum)
         served[storage] = dict(_percentiles(ttr), mlups=round(st["cell_steps"] / span / 1e6, 1),
                                makespan_s=round(span, 3), rounds=st["rounds"],
@@ -313,6 +318,7 @@ def run_serve(args):
             "arena_bytes": arena,
         },
         "time_to_result": {"served_f32": served["f32"], "served_f16": served["f16"],
+                           "served_f16l": served["f16l"],
                            "sequential_fp64": seq,
                            "p99_speedup_f32_vs_sequential_fp64":
                                round(seq["p99_s"] / served["f32"]["p99_s"], 2),
