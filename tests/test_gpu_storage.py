@@ -65,16 +65,20 @@ def test_initial_state_is_rounded_equilibrium(oracle, storage):
     assert np.array_equal(g, f) or np.abs(g - f).max() <= 4 * np.finfo(float).eps
 
 
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
 @pytest.mark.parametrize("storage", ["f32", "f16", "f16l"])
-def test_launch_shapes_bitwise_identical(storage):
+def test_launch_shapes_bitwise_identical(storage, collision):
+    # Each unrolled copy of the row body must round alike: a launch shape
+    # changes which copy computes a row (with binary16 storage and MRT a
+    # mixed-precision fma folded into some copies once broke this).
     require_gpu()
-    p = W.params(301, 203, tr=0.8, storage=storage)
+    p = W.params(301, 203, tr=0.8, storage=storage, collision=collision)
     rg, rl = W.unit_cs_coexistence(0.8)
     rho0 = W.smooth_random(301, 203, 12, mean=0.5 * (rg + rl), amplitude=0.5 * (rl - rg))
     p["rho_ref"] = W.shift_reference(rho0, storage)
     ref = gpu_lattice(p, rho0)
     ref.step(20)
-    for launch in ((64, 3), (128, 7), (384, 5)):
+    for launch in ((64, 3), (128, 7), (384, 5), (256, 203)):
         lat = gpu_lattice(p, rho0, launch=launch)
         lat.step(20)
         assert torch.equal(ref.populations(), lat.populations()), launch
