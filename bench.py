@@ -4,15 +4,20 @@ Workload: four 2048 x 2048 periodic lattices, each a flat liquid slab in the
 middle half of the domain (tanh interfaces of width 2, seeded U(+-1e-3) noise)
 of the Carnahan-Starling EOS (a=1, b=4, R=1 convention) at reduced
 temperatures 0.6, 0.7, 0.8 and 0.9, BGK tau = 1, G = -1, eps = 1.73, sigma = 1.
-One bench step advances each of the four lattices by one time step (one
-fused kernel launch per lattice).  Inputs are resident in HBM before timing.
+One bench step advances each of the four lattices by one time step.  The
+library takes two time steps per kernel launch (the two-step pass: read the
+populations once, compute both steps, write once), so the steps are issued in
+pairs, one launch per lattice per pair; an odd step count ends with one
+single-step launch per lattice.  Inputs are resident in HBM before timing.
 
 Output: one JSON line.  `value` is lattice updates per second over the timed
-steps (MLUPS).  `roofline` prices the step kernel against the 8 TB/s HBM peak
-with 144 algorithmic bytes per cell update (9 FP64 populations read + 9
-written), using the kernel's average duration timed with HIP events on the
-library's stream.  `cpu_baseline` times the CPU oracle on a bounded sample of
-the same workload.
+steps (MLUPS).  `roofline` prices the dominant kernel (the two-step pass; the
+single-step sweep for the per-cell-reference FP16 mode, which has no two-step
+kernel) against the 8 TB/s HBM peak with its algorithmic bytes per launch: 144
+per cell for FP64 (9 populations read + 9 written once per launch, whether the
+launch advances one step or two), using the kernel's average duration timed
+with HIP events on the library's stream.  `cpu_baseline` times the CPU oracle
+on a bounded sample of the same workload.
 
 --storage f32 / f16 runs the same workload with populations stored as FP32 /
 FP16 deviations from w_i rho_ref (FP32 arithmetic; 72 / 36 bytes per cell).
@@ -44,14 +49,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# 9 reads + 9 writes per cell update (and, for f16l, the per-cell FP32 reference)
+# 9 reads + 9 writes per cell and launch (and, for f16l, the per-cell FP32
+# reference): per cell update for single steps, per two updates for the
+# two-step pass
 BYTES_PER_CELL = {"f64": 144, "f32": 72, "f16": 36, "f16l": 44}
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 METRIC = "MLUPS/GPU and % HBM roofline (FP64 vs FP32/FP16-shifted); p50/p99 time-to-result"
 N = 2048
 TEMPS = (0.6, 0.7, 0.8, 0.9)
 KERNEL_SRC = os.path.join(ROOT, "paper_2003_07968_amd", "csrc", "lbm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_{storage}_2048.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{storage}_2048.json")
 
 
 def err(msg):
@@ -63,10 +70,10 @@ def source_digest():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(storage):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
-    path = TRAFFIC_FILE.format(storage=storage)
+def measured_traffic(kernel, storage):
+    """HBM bytes per launch of `kernel` ("pass2" or "step") from the committed
+    rocprofv3 counter runs, if they were taken on the current kernel source."""
+    path = TRAFFIC_FILE.format(kernel=kernel, storage=storage)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -371,40 +378,58 @@ def main():
         p["collision"] = W.COLLISION[args.collision]
         lats.append(lbm.Lattice(p, rho0))
     launch = lats[0].launch()
-    err(f"lattices ready, launch shape {launch}")
+    fusion = lats[0].fusion()
+    err(f"lattices ready, {fusion} step(s) per launch, launch shape {launch}")
 
-    for _ in range(args.warmup):
-        for lat in lats:
-            lat.step(1)
+    def advance(nsteps):
+        for _ in range(nsteps // 2):
+            for lat in lats:
+                lat.step(2)
+        for _ in range(nsteps % 2):
+            for lat in lats:
+                lat.step(1)
+
+    advance(args.warmup)
     torch.cuda.synchronize()
     for lat in lats:
         lat.sync()
     err(f"warmup {args.warmup} steps done")
 
+    # the library's stream is torch's current stream: events on it bracket
+    # exactly the step kernels; em splits the paired steps from the odd one
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
+    em = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    pairs, odd = divmod(args.steps, 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
-        for lat in lats:
-            lat.step(1)
+    advance(2 * pairs)
+    em.record(stream)
+    advance(odd)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     for lat in lats:
         lat.sync()   # raises on a sticky domain error
     gpu_ms = e0.elapsed_time(e1)
+    pair_ms = e0.elapsed_time(em)
     err(f"timed {args.steps} steps: {gpu_ms:.2f} ms on the stream, {wall * 1e3:.2f} ms wall")
 
     cells = N * N * len(lats)
     seconds = gpu_ms / 1e3
     mlups = cells * args.steps / seconds / 1e6
-    launch_ms = gpu_ms / (args.steps * len(lats))
+    # dominant kernel: the two-step pass when the steps came in pairs
+    if fusion == 2 and pairs > 0:
+        kernel, launch_ms = "pass2", pair_ms / (pairs * len(lats))
+        kname = "sweep2_kernel (two steps per launch"
+    else:
+        kernel, launch_ms = "step", gpu_ms / (args.steps * len(lats))
+        kname = "sweep_kernel (one step per launch"
     bpc = BYTES_PER_CELL[args.storage]
     achieved = bpc * N * N / (launch_ms / 1e3) / 1e9
-    traffic = measured_traffic(args.storage) if args.collision == "bgk" else None
+    traffic = measured_traffic(kernel, args.storage) if args.collision == "bgk" else None
 
     out = {
         "metric": METRIC,
@@ -427,7 +452,8 @@ def main():
                         "eps=1.73, sigma=1, W=2, seeded +-1e-3 noise",
             "storage": args.storage, "collision": args.collision,
             "lattices": len(lats), "nx": N, "ny": N,
-            "bytes_per_cell_update": bpc,
+            "steps_per_launch": fusion,
+            "bytes_per_cell_and_launch": bpc,
             "launch_block_x_seg_rows_workgroups": list(launch),
         },
         "roofline": {
@@ -437,7 +463,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"sweep_kernel (step mode, {args.storage} storage, {args.collision})",
+            "kernel": f"{kname}, {args.storage} storage, {args.collision})",
             "kernel_avg_ms": round(launch_ms, 5),
         },
     }

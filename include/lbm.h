@@ -188,22 +188,44 @@ lbm_status lbm_set_populations(lbm_handle *h, const double *d_f, int64_t t);
 /* Number of completed steps. */
 int64_t lbm_time(const lbm_handle *h);
 
-/* Override the launch shape of the sweep kernels: block_x threads per
- * workgroup (a multiple of 64 in [64, 512]; each workgroup owns block_x - 2
- * columns) and seg_rows rows walked by each workgroup (>= 1).  0 keeps the
- * library's choice.  Every shape gives bitwise-identical populations. */
+/* Override the launch shape of the single-step sweep kernels (the moments and
+ * diagnostics sweeps, and lbm_step when it takes single steps): block_x
+ * threads per workgroup (a multiple of 64 in [64, 512]; each workgroup owns
+ * block_x - 2 columns) and seg_rows rows walked by each workgroup (>= 1).  0
+ * keeps the library's choice.  Every shape gives bitwise-identical
+ * populations. */
 lbm_status lbm_set_launch(lbm_handle *h, int32_t block_x, int32_t seg_rows);
 
-/* The launch shape in use: out[0] = block_x, out[1] = seg_rows,
- * out[2] = workgroups per step. */
+/* Time steps per pass of the step kernel, 1 or 2.  With 2, lbm_step advances
+ * pairs of steps in one pass that reads and writes the populations once: each
+ * workgroup computes the first step (time t) on its tile and a halo of three
+ * columns and three rows on each side, keeps it on chip, and computes and
+ * stores the second (time t + 1) on its tile; an odd remainder takes a single
+ * step.  The results are bitwise those of single steps (the state between the
+ * two is rounded to the storage type as a single step stores it), and so is
+ * the first domain error reported by lbm_sync.  block_x (128, 256 or 512;
+ * each workgroup owns block_x - 6 columns, rounded down to the strip
+ * alignment) and seg_rows (>= 1) set the two-step launch shape; 0 keeps the
+ * library's choice (256 threads, 16 rows).  lbm_init selects 2 for every
+ * storage mode but LBM_STORE_F16_LOCAL, which has no two-step kernel (there
+ * steps = 2 is LBM_ERR_INVALID_ARG).  Batches always take single steps. */
+lbm_status lbm_set_fusion(lbm_handle *h, int32_t steps, int32_t block_x, int32_t seg_rows);
+
+/* Time steps per pass in use (1 or 2); -1 for a NULL handle. */
+int32_t lbm_get_fusion(const lbm_handle *h);
+
+/* The launch shape of the step kernel in use (the two-step pass's when
+ * lbm_get_fusion is 2): out[0] = block_x, out[1] = seg_rows, out[2] =
+ * workgroups per launch. */
 lbm_status lbm_get_launch(const lbm_handle *h, int32_t out[3]);
 
-/* Pick the launch shape by measurement: time a few step launches for each
- * candidate shape (workgroup widths 64..512, segment lengths 3..17 rows) and
- * keep the fastest.  The timed launches write only the spare population
- * buffer and are not counted as steps, so the state and t are unchanged.
- * Synchronous; out (may be NULL) receives the chosen block_x, seg_rows and the
- * measured microseconds per step. */
+/* Pick the launch shape of the step kernel in use by measurement: time a few
+ * launches for each candidate shape (single steps: workgroup widths 64..512,
+ * segments of 3..17 rows; two-step pass: widths 128, 256, 512, segments of
+ * 8..32 rows) and keep the fastest.  The timed launches write only the spare
+ * population buffer and are not counted as steps, so the state and t are
+ * unchanged.  Synchronous; out (may be NULL) receives the chosen block_x,
+ * seg_rows and the measured microseconds per time step. */
 lbm_status lbm_autotune(lbm_handle *h, double out[3]);
 
 /* ---- Batches: many lattices advanced together by one kernel launch per step ----

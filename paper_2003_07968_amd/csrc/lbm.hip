@@ -833,6 +833,201 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(c
                                                nullptr, nullptr);
 }
 
+// Two time steps in one pass, t -> t + 2: the populations are read once and
+// written once for two updates.  Step A (time t) is the single-step update on
+// the loaded rows; its post-collision rows go to a ring of three LDS rows,
+// from which step B (time t + 1) pulls.  The update of a cell depends on the
+// cells within two of it, so B's output strip is narrower than A's by three
+// columns on each side (A's force needs psi one column beyond, B pulls one
+// column beyond A's valid results, and B's force needs psi one column beyond
+// that), and B's output rows [0, n) need A's rows [-2, n + 1] and psi of A's
+// rows [-3, n + 2].  Both steps call the same routines as the single-step
+// walk, in the same order, so the result is bitwise that of two single steps.
+//
+// The walk runs m = 0 .. n + 5; at iteration m it prefetches A's populations
+// of row m - 3 + PF, turns row m - 3 into psi, collides A's row m - 4 into the
+// ring, pulls B's row m - 5 from the ring and turns it into psi, and collides
+// and stores B's row m - 6.  Register sets rotate with period 6 (the loop is
+// unrolled six times).
+template <int BX, int PF, int FORCE, int ST, int COLL>
+__device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ src,
+                                      typename Store<ST>::E *__restrict__ dst, const Coeffs &c,
+                                      long long t, int ys, int n, int x, const Cols &cols,
+                                      bool active, bool valid_b, bool interior,
+                                      typename Store<ST>::R *lds_a, typename Store<ST>::R *lds_b,
+                                      typename Store<ST>::R *ring, unsigned long long &bad)
+{
+    using E = typename Store<ST>::E;
+    using R = typename Store<ST>::R;
+    static_assert(PF == 1, "the period-6 rotation assumes one row of prefetch");
+    constexpr int K = PF + 2;
+    const Phys<R> P(c);
+    const R gref = (R)c.rho_ref;
+    const int tx = threadIdx.x;
+    const int txm = tx > 0 ? tx - 1 : 0, txp = tx < BX - 1 ? tx + 1 : BX - 1;
+    auto lrow = [&](int s) {
+        const int r = (ys + s) % c.ny;
+        return r < 0 ? r + c.ny : r;
+    };
+    auto check = [&](bool ok, long long step, int s) {
+        if (!ok) bad = min(bad, domain_key(step, lrow(s), x, c.nx));
+    };
+
+    R fa[K][kQ], fb[2][kQ];
+    Row<R> pa[3], pb[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        pa[k] = pb[k] = Row<R>{R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            fa[k][i] = R(0);
+        fb[0][i] = fb[1][i] = R(0);
+    }
+    // prologue: A's populations of rows -3 .. -4 + PF
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+        load_pulled<ST>(src, c, lrow(-3 + p), cols, fa[(1 + p) % K]);
+
+    auto body = [&](auto Jc, int m) {
+        constexpr int J = decltype(Jc)::value;  // m % 6
+        constexpr int a_cur = J % K, a_lead = (J + 1) % K, a_fetch = (J + 1 + PF) % K;
+        {
+            const int s = m - 3 + PF;
+            load_pulled<ST>(src, c, lrow(s < n + 2 ? s : n + 2), cols, fa[a_fetch]);
+        }
+        // step A: psi of row m - 3 (always one of A's rows -3 .. n + 2)
+        Row<R> &LA = pa[(J + 2) % 3];
+        {
+            const bool ok = rho_psi<FORCE, R>(fa[a_lead], gref, P, LA.rho, LA.o);
+            if (active) check(ok, t, m - 3);
+            R *buf = lds_a + (m & 1) * BX;
+            buf[tx] = LA.o;
+            __syncthreads();
+            LA.l = buf[txm];
+            LA.r = buf[txp];
+        }
+        // step A: collision of row m - 4 into the ring
+        {
+            const Row<R> &TA = pa[J % 3], &CA = pa[(J + 1) % 3];
+            R Fx = R(0), Fy = R(0);
+            if (FORCE) {
+                R sv[kQ];
+                stencil<+1, R>(TA, CA, LA, sv);
+                force<R>(sv, P, Fx, Fy);
+            }
+            R ux, uy;
+            velocity<R>(fa[a_cur], CA.rho, Fx, Fy, ux, uy);
+            if constexpr (COLL == LBM_COLL_MRT)
+                collide_mrt<R>(fa[a_cur], CA.rho, ux, uy, Fx, Fy, P);
+            else
+                collide<R>(fa[a_cur], gref, CA.rho, ux, uy, Fx, Fy, P);
+            // rounded to the storage type, as a single step stores them
+            R *w = ring + ((J + 2) % 3) * kQ * BX;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i)
+                w[i * BX + tx] = (R)(E)fa[a_cur][i];
+            __syncthreads();
+        }
+        // step B: pull row m - 5 from A's rows m - 6, m - 5, m - 4, and its psi
+        Row<R> &LB = pb[(J + 2) % 3];
+        {
+            const R *rm = ring + (J % 3) * kQ * BX;        // lattice row r - 1
+            const R *rc = ring + ((J + 1) % 3) * kQ * BX;  // row r
+            const R *rp = ring + ((J + 2) % 3) * kQ * BX;  // row r + 1
+            R *g = fb[(J + 1) % 2];
+            g[0] = rc[0 * BX + tx];
+            g[1] = rc[1 * BX + txm];
+            g[2] = rm[2 * BX + tx];
+            g[3] = rc[3 * BX + txp];
+            g[4] = rp[4 * BX + tx];
+            g[5] = rm[5 * BX + txm];
+            g[6] = rm[6 * BX + txp];
+            g[7] = rp[7 * BX + txp];
+            g[8] = rp[8 * BX + txm];
+            const bool ok = rho_psi<FORCE, R>(g, gref, P, LB.rho, LB.o);
+            if (valid_b && m - 5 >= -1) check(ok, t + 1, m - 5);
+            R *buf = lds_b + (m & 1) * BX;
+            buf[tx] = LB.o;
+            __syncthreads();
+            LB.l = buf[txm];
+            LB.r = buf[txp];
+        }
+        // step B: collision of row m - 6 and its store
+        {
+            const Row<R> &TB = pb[J % 3], &CB = pb[(J + 1) % 3];
+            R *g = fb[J % 2];
+            R Fx = R(0), Fy = R(0);
+            if (FORCE) {
+                R sv[kQ];
+                stencil<+1, R>(TB, CB, LB, sv);
+                force<R>(sv, P, Fx, Fy);
+            }
+            R ux, uy;
+            velocity<R>(g, CB.rho, Fx, Fy, ux, uy);
+            if constexpr (COLL == LBM_COLL_MRT)
+                collide_mrt<R>(g, CB.rho, ux, uy, Fx, Fy, P);
+            else
+                collide<R>(g, gref, CB.rho, ux, uy, Fx, Fy, P);
+            const int sb = m - 6;
+            if (interior && sb >= 0 && sb < n) {
+                const size_t prow = (size_t)lrow(sb) * c.pitch;
+#pragma unroll
+                for (int i = 0; i < kQ; ++i)
+                    __builtin_nontemporal_store(
+                        (E)g[i], (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+            }
+        }
+    };
+
+    constexpr int U = 6;
+    const int total = n + 6;
+    int m = 0;
+    for (; m + U <= total; m += U)
+        unroll([&](auto J) { body(J, m + decltype(J)::value); },
+               std::make_integer_sequence<int, U>{});
+    unroll([&](auto J) {
+        if (m + decltype(J)::value < total) body(J, m + decltype(J)::value);
+    }, std::make_integer_sequence<int, U - 1>{});
+}
+
+// Halo columns of the two-step pass on each side of its output strip.
+constexpr int kHalo2 = 3;
+
+// One tile of the two-step pass: output strip `strip` of row band `seg`.
+template <int BX, int PF, int FORCE, int ST, int COLL>
+__global__ __launch_bounds__(BX) void sweep2_kernel(const void *__restrict__ src_v,
+                                                    void *__restrict__ dst_v, Coeffs c, Tiles tl,
+                                                    long long t,
+                                                    unsigned long long *__restrict__ err)
+{
+    using E = typename Store<ST>::E;
+    using R = typename Store<ST>::R;
+    __shared__ R lds_a[2 * BX], lds_b[2 * BX], ring[3 * kQ * BX];
+    const int tile = xcd_tile(blockIdx.x, tl.ntiles);
+    const int seg = tile / tl.nstrips;
+    const int strip = tile - seg * tl.nstrips;
+    const int xs = strip * tl.width;
+    const int xe = min(c.nx, xs + tl.width);
+    const int ys = (int)((long long)seg * c.ny / tl.nseg);
+    const int ye = (int)((long long)(seg + 1) * c.ny / tl.nseg);
+    const int tx = threadIdx.x;
+    const int width = xe - xs;  // output columns, <= BX - 2 kHalo2
+    const bool active = tx < width + 2 * kHalo2;
+    const bool valid_b = tx >= kHalo2 - 1 && tx <= width + kHalo2;
+    const bool interior = tx >= kHalo2 && tx < width + kHalo2;
+    int x = (xs - kHalo2 + (active ? tx : kHalo2)) % c.nx;
+    x = x < 0 ? x + c.nx : x;
+    const int xm = wrap_lo(x - 1, c.nx), xp = wrap_hi(x + 1, c.nx);
+    constexpr uint32_t es = sizeof(E);
+    const Cols cols{(uint32_t)x * es, (uint32_t)xm * es, (uint32_t)xp * es};
+    unsigned long long bad = ~0ull;
+    walk2<BX, PF, FORCE, ST, COLL>((const E *)src_v, (E *)dst_v, c, t, ys, ye - ys, x, cols, active,
+                                   valid_b, interior, lds_a, lds_b, ring, bad);
+    if (bad != ~0ull) atomicMin(err, bad);
+}
+
 __global__ void bump_counter(long long *p) { *p += 1; }
 __global__ void set_counter(long long *p, long long v) { *p = v; }
 
@@ -987,6 +1182,9 @@ struct lbm_handle {
     int64_t t;
     int bx, seg_rows;
     Tiles tiles;
+    int fuse;                // time steps per pass of the step kernel (1 or 2)
+    int bx2, seg_rows2;      // launch shape of the two-step pass
+    Tiles tiles2;
     lbm_status sticky;
     std::string last_error;
 };
@@ -1136,6 +1334,22 @@ bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl,
     return true;
 }
 
+// Tiles of the two-step pass: kHalo2 halo columns on each side of a strip.
+bool make_tiles2(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl)
+{
+    int w = bx - 2 * kHalo2;
+    if (nx > w) w = w / align * align;
+    else w = nx;
+    if (w < 1) return false;
+    tl->width = w;
+    tl->nstrips = (nx + w - 1) / w;
+    tl->nseg = (ny + seg_rows - 1) / seg_rows;
+    const long long nt = (long long)tl->nstrips * tl->nseg;
+    if (nt > kMaxTiles) return false;
+    tl->ntiles = (int)nt;
+    return true;
+}
+
 // Default launch shape: 256-thread workgroups unless another width wastes
 // clearly fewer lanes on ragged strips (small lattices), then row segments
 // short enough for about 64 waves per CU on 256 CUs (20 for FP16 storage, 28
@@ -1175,6 +1389,25 @@ void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
     *rows_out = rows;
 }
 
+// Default shape of the two-step pass: 256 threads, 16-row segments.  Measured
+// on 2048 x 2048 over 128..512 threads and 8..32 rows: FP64 and FP16 are
+// fastest at (256, 16..20), FP32 at (256, 12..20); 512 threads (one
+// workgroup per CU) are clearly slower.
+constexpr int kFuseBx = 256, kFuseRows = 16;
+
+// Default segment length of the two-step pass: kFuseRows, or longer where the
+// lattice would need more than kMaxTiles workgroups.  False if no length fits.
+bool default_rows2(int nx, int ny, int storage, int bx, int *rows, Tiles *tl)
+{
+    for (int r = std::min(kFuseRows, ny);; r = std::min(2 * r, ny)) {
+        if (make_tiles2(nx, ny, bx, r, strip_align(storage), tl)) {
+            *rows = r;
+            return true;
+        }
+        if (r == ny) return false;
+    }
+}
+
 lbm_status dev_fail(lbm_handle *h, hipError_t e, const char *what)
 {
     if (h) {
@@ -1209,6 +1442,50 @@ hipError_t launch_sweep_t(lbm_handle *h, const void *src, void *dst, Fields fo)
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int FORCE, int ST, int COLL>
+hipError_t launch_sweep2_t(lbm_handle *h, const void *src, void *dst)
+{
+    const dim3 grid((unsigned)h->tiles2.ntiles);
+    switch (h->bx2) {
+#define LBM_CASE(BX)                                                                          \
+    case BX:                                                                                  \
+        hipLaunchKernelGGL((sweep2_kernel<BX, 1, FORCE, ST, COLL>), grid, dim3(BX), 0,         \
+                           h->stream, src, dst, h->c, h->tiles2, (long long)h->t, h->err);    \
+        break;
+        LBM_CASE(128)
+        LBM_CASE(256)
+        LBM_CASE(512)
+#undef LBM_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int FORCE, int ST>
+hipError_t launch_sweep2_c(lbm_handle *h, const void *src, void *dst)
+{
+    return h->c.coll == LBM_COLL_MRT ? launch_sweep2_t<FORCE, ST, LBM_COLL_MRT>(h, src, dst)
+                                     : launch_sweep2_t<FORCE, ST, LBM_COLL_BGK>(h, src, dst);
+}
+
+template <int FORCE>
+hipError_t launch_sweep2_f(lbm_handle *h, const void *src, void *dst)
+{
+    switch (h->c.storage) {
+    case LBM_STORE_F64: return launch_sweep2_c<FORCE, LBM_STORE_F64>(h, src, dst);
+    case LBM_STORE_F32_SHIFTED: return launch_sweep2_c<FORCE, LBM_STORE_F32_SHIFTED>(h, src, dst);
+    case LBM_STORE_F16_SHIFTED: return launch_sweep2_c<FORCE, LBM_STORE_F16_SHIFTED>(h, src, dst);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Two time steps, t -> t + 2, in one pass.
+hipError_t launch_sweep2(lbm_handle *h, const void *src, void *dst)
+{
+    return h->c.force_on ? launch_sweep2_f<1>(h, src, dst) : launch_sweep2_f<0>(h, src, dst);
 }
 
 // The collision operator enters only the step sweep.
@@ -1390,6 +1667,8 @@ double time_launches(hipStream_t stream, int reps, Fn &&fn)
 
 const int kTuneWidths[] = {64, 128, 192, 256, 320, 384, 512};
 const int kTuneRows[] = {3, 5, 7, 9, 13, 17};
+const int kTuneWidths2[] = {128, 256, 512};
+const int kTuneRows2[] = {8, 12, 16, 20, 24, 32};
 
 // Rebuild and upload the batch table for the current members and shape.
 // Synchronous (the host staging vector is reused by the next upload).
@@ -1524,6 +1803,13 @@ lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspac
         delete h;
         return LBM_ERR_INVALID_ARG;
     }
+    // two steps per pass wherever the storage mode has the two-step kernel
+    h->bx2 = kFuseBx;
+    h->fuse = params->storage != LBM_STORE_F16_LOCAL &&
+                      default_rows2(params->nx, params->ny, params->storage, h->bx2,
+                                    &h->seg_rows2, &h->tiles2)
+                  ? 2
+                  : 1;
 
     const size_t n = (size_t)params->nx * params->ny;
     const unsigned blocks = (unsigned)((n + 255) / 256);
@@ -1546,7 +1832,16 @@ lbm_status lbm_step(lbm_handle *h, int64_t nsteps)
         h->last_error = "nsteps must be >= 0";
         return LBM_ERR_INVALID_ARG;
     }
-    for (int64_t k = 0; k < nsteps; ++k) {
+    int64_t k = 0;
+    if (h->fuse == 2) {
+        for (; k + 2 <= nsteps; k += 2) {
+            hipError_t e = launch_sweep2(h, h->cur, h->nxt);
+            if (e != hipSuccess) return dev_fail(h, e, "launching the two-step kernel");
+            std::swap(h->cur, h->nxt);
+            h->t += 2;
+        }
+    }
+    for (; k < nsteps; ++k) {
         hipError_t e = launch_sweep<kStep>(h, h->cur, h->nxt, Fields{});
         if (e != hipSuccess) return dev_fail(h, e, "launching the step kernel");
         std::swap(h->cur, h->nxt);
@@ -1632,19 +1927,94 @@ lbm_status lbm_set_launch(lbm_handle *h, int32_t block_x, int32_t seg_rows)
     return LBM_OK;
 }
 
+lbm_status lbm_set_fusion(lbm_handle *h, int32_t steps, int32_t block_x, int32_t seg_rows)
+{
+    if (!h) return LBM_ERR_INVALID_ARG;
+    if (steps == 1) {
+        h->fuse = 1;
+        return LBM_OK;
+    }
+    if (steps != 2) {
+        h->last_error = "steps per pass must be 1 or 2";
+        return LBM_ERR_INVALID_ARG;
+    }
+    if (h->p.storage == LBM_STORE_F16_LOCAL) {
+        h->last_error = "the two-step pass does not support the per-cell reference storage";
+        return LBM_ERR_INVALID_ARG;
+    }
+    const int bx = block_x != 0 ? block_x : kFuseBx;
+    if ((bx != 128 && bx != 256 && bx != 512) || seg_rows < 0) {
+        h->last_error = "block_x must be 128, 256 or 512 and seg_rows >= 1";
+        return LBM_ERR_INVALID_ARG;
+    }
+    int rows = seg_rows;
+    Tiles tl;
+    if (rows == 0 ? !default_rows2(h->p.nx, h->p.ny, h->p.storage, bx, &rows, &tl)
+                  : !make_tiles2(h->p.nx, h->p.ny, bx, rows, strip_align(h->p.storage), &tl)) {
+        h->last_error = "launch shape needs too many workgroups";
+        return LBM_ERR_INVALID_ARG;
+    }
+    h->fuse = 2;
+    h->bx2 = bx;
+    h->seg_rows2 = rows;
+    h->tiles2 = tl;
+    return LBM_OK;
+}
+
 lbm_status lbm_get_launch(const lbm_handle *h, int32_t out[3])
 {
     if (!h || !out) return LBM_ERR_INVALID_ARG;
-    out[0] = h->bx;
-    out[1] = h->seg_rows;
-    out[2] = h->tiles.ntiles;
+    const bool two = h->fuse == 2;
+    out[0] = two ? h->bx2 : h->bx;
+    out[1] = two ? h->seg_rows2 : h->seg_rows;
+    out[2] = two ? h->tiles2.ntiles : h->tiles.ntiles;
     return LBM_OK;
 }
+
+int32_t lbm_get_fusion(const lbm_handle *h) { return h ? h->fuse : -1; }
 
 lbm_status lbm_autotune(lbm_handle *h, double out[3])
 {
     if (!h) return LBM_ERR_INVALID_ARG;
     const int align = strip_align(h->p.storage);
+    if (h->fuse == 2) {
+        const int bx0 = h->bx2, rows0 = h->seg_rows2;
+        const Tiles tl0 = h->tiles2;
+        double best = 1e300;
+        int best_bx = bx0, best_rows = rows0;
+        for (int bx : kTuneWidths2)
+            for (int rows : kTuneRows2) {
+                Tiles tl;
+                const int r = std::min(rows, h->p.ny);
+                if (!make_tiles2(h->p.nx, h->p.ny, bx, r, align, &tl)) continue;
+                h->bx2 = bx;
+                h->seg_rows2 = r;
+                h->tiles2 = tl;
+                // cur -> nxt without swapping: the state is not advanced
+                const double us = time_launches(
+                    h->stream, 3, [&] { return launch_sweep2(h, h->cur, h->nxt); });
+                if (us < 0) {
+                    h->bx2 = bx0;
+                    h->seg_rows2 = rows0;
+                    h->tiles2 = tl0;
+                    return dev_fail(h, hipGetLastError(), "timing a launch shape");
+                }
+                if (us < best) {
+                    best = us;
+                    best_bx = bx;
+                    best_rows = r;
+                }
+            }
+        make_tiles2(h->p.nx, h->p.ny, best_bx, best_rows, align, &h->tiles2);
+        h->bx2 = best_bx;
+        h->seg_rows2 = best_rows;
+        if (out) {
+            out[0] = best_bx;
+            out[1] = best_rows;
+            out[2] = 0.5 * best;  // per time step
+        }
+        return LBM_OK;
+    }
     const int bx0 = h->bx, rows0 = h->seg_rows;
     const Tiles tl0 = h->tiles;
     double best = 1e300;

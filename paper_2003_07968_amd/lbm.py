@@ -103,6 +103,10 @@ def _load():
         lib.lbm_time.restype = ctypes.c_int64
         lib.lbm_set_launch.argtypes = [H, ctypes.c_int32, ctypes.c_int32]
         lib.lbm_set_launch.restype = ctypes.c_int
+        lib.lbm_set_fusion.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        lib.lbm_set_fusion.restype = ctypes.c_int
+        lib.lbm_get_fusion.argtypes = [H]
+        lib.lbm_get_fusion.restype = ctypes.c_int32
         lib.lbm_get_launch.argtypes = [H, ctypes.POINTER(ctypes.c_int32)]
         lib.lbm_get_launch.restype = ctypes.c_int
         lib.lbm_status_string.argtypes = [ctypes.c_int]
@@ -157,7 +161,7 @@ def _load():
 
 EXPORTED = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_sync", "lbm_moments",
             "lbm_diagnostics", "lbm_get_populations", "lbm_set_populations", "lbm_time",
-            "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_batch_workspace_bytes",
+            "lbm_set_launch", "lbm_set_fusion", "lbm_get_fusion", "lbm_get_launch", "lbm_autotune", "lbm_batch_workspace_bytes",
             "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
             "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_destroy", "lbm_status_string",
             "lbm_last_error", "lbm_destroy", "lbm_server_create", "lbm_server_job_bytes",
@@ -243,6 +247,14 @@ def lbm_time(h):
 
 def lbm_set_launch(h, block_x=0, seg_rows=0):
     _check(h, _load().lbm_set_launch(h, int(block_x), int(seg_rows)))
+
+
+def lbm_set_fusion(h, steps, block_x=0, seg_rows=0):
+    _check(h, _load().lbm_set_fusion(h, int(steps), int(block_x), int(seg_rows)))
+
+
+def lbm_get_fusion(h):
+    return _load().lbm_get_fusion(h)
 
 
 def lbm_get_launch(h):
@@ -420,6 +432,12 @@ class Lattice:
 
     def set_launch(self, block_x=0, seg_rows=0):
         lbm_set_launch(self.handle, block_x, seg_rows)
+
+    def set_fusion(self, steps, block_x=0, seg_rows=0):
+        lbm_set_fusion(self.handle, steps, block_x, seg_rows)
+
+    def fusion(self):
+        return lbm_get_fusion(self.handle)
 
     def launch(self):
         return lbm_get_launch(self.handle)

@@ -24,11 +24,17 @@ def log(msg):
     sys.stdout.flush()
 
 
-def gpu_lattice(p, rho0, ux0=None, uy0=None, launch=None):
+def gpu_lattice(p, rho0, ux0=None, uy0=None, launch=None, fusion=None):
+    """A lattice on the GPU.  launch = (block_x, seg_rows) selects single steps
+    in that shape; fusion = (steps, block_x, seg_rows) the steps per pass and
+    the two-step shape.  Neither: the library's defaults."""
     from paper_2003_07968_amd import lbm
     lat = lbm.Lattice(p, rho0, ux0, uy0)
     if launch is not None:
+        lat.set_fusion(1)
         lat.set_launch(*launch)
+    if fusion is not None:
+        lat.set_fusion(*fusion)
     return lat
 
 

@@ -79,3 +79,14 @@ def test_status_strings(lib):
         assert lib.lbm_status_string(st)
     assert lib.lbm_last_error(None) == b""
     assert lib.lbm_time(None) == -1
+
+
+def test_null_handle_rejected_by_host_entry_points(lib):
+    from paper_2003_07968_amd import lbm
+    out = (ctypes.c_int32 * 3)()
+    assert lib.lbm_set_fusion(None, 2, 0, 0) == lbm.LBM_ERR_INVALID_ARG
+    assert lib.lbm_set_fusion(None, 1, 0, 0) == lbm.LBM_ERR_INVALID_ARG
+    assert lib.lbm_get_fusion(None) == -1
+    assert lib.lbm_set_launch(None, 256, 8) == lbm.LBM_ERR_INVALID_ARG
+    assert lib.lbm_get_launch(None, out) == lbm.LBM_ERR_INVALID_ARG
+    assert lib.lbm_step(None, 1) == lbm.LBM_ERR_INVALID_ARG
