@@ -34,8 +34,8 @@ server (FP32- and FP16-shifted) and reports p50/p99 time-to-result beside the
 same jobs run one after another on the plain FP64 path.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--storage f64|f32|f16] [--collision bgk|mrt]
-                       [--workload slab|batch|serve] [--jobs J]
+                       [--storage f64|f32|f16|f16l] [--collision bgk|mrt]
+                       [--fusion 1|2] [--workload slab|batch|serve] [--jobs J]
        python bench.py --copy-calibration   (plain copy kernel for PMC scaling)
 """
 import argparse
@@ -345,6 +345,8 @@ def main():
     ap.add_argument("--storage", choices=sorted(BYTES_PER_CELL), default="f64")
     ap.add_argument("--collision", choices=("bgk", "mrt"), default="bgk")
     ap.add_argument("--workload", choices=("slab", "batch", "serve"), default="slab")
+    ap.add_argument("--fusion", type=int, choices=(1, 2), default=None,
+                    help="time steps per launch (default: the library's choice)")
     ap.add_argument("--jobs", type=int, default=64, help="jobs in the serving stream")
     args = ap.parse_args()
 
@@ -377,6 +379,8 @@ def main():
         p["rho_ref"] = W.shift_reference(rho0, args.storage)
         p["collision"] = W.COLLISION[args.collision]
         lats.append(lbm.Lattice(p, rho0))
+        if args.fusion is not None:
+            lats[-1].set_fusion(args.fusion)
     launch = lats[0].launch()
     fusion = lats[0].fusion()
     err(f"lattices ready, {fusion} step(s) per launch, launch shape {launch}")
