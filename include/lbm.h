@@ -206,7 +206,9 @@ lbm_status lbm_set_launch(lbm_handle *h, int32_t block_x, int32_t seg_rows);
  * the first domain error reported by lbm_sync.  block_x (128, 256 or 512;
  * each workgroup owns block_x - 6 columns, rounded down to the strip
  * alignment) and seg_rows (>= 1) set the two-step launch shape; 0 keeps the
- * library's choice (256 threads, 16 rows).  lbm_init selects 2 for every
+ * library's choice (256 threads; segments as long as fill whole rounds of the
+ * workgroups the device runs at once, 24..40 rows, 12..40 for FP16 storage,
+ * fewer on small lattices).  lbm_init selects 2 for every
  * storage mode but LBM_STORE_F16_LOCAL, which has no two-step kernel (there
  * steps = 2 is LBM_ERR_INVALID_ARG).  Batches always take single steps. */
 lbm_status lbm_set_fusion(lbm_handle *h, int32_t steps, int32_t block_x, int32_t seg_rows);

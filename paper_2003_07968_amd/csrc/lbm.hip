@@ -835,27 +835,44 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(c
 
 // Two time steps in one pass, t -> t + 2: the populations are read once and
 // written once for two updates.  Step A (time t) is the single-step update on
-// the loaded rows; its post-collision rows go to a ring of three LDS rows,
-// from which step B (time t + 1) pulls.  The update of a cell depends on the
-// cells within two of it, so B's output strip is narrower than A's by three
-// columns on each side (A's force needs psi one column beyond, B pulls one
-// column beyond A's valid results, and B's force needs psi one column beyond
-// that), and B's output rows [0, n) need A's rows [-2, n + 1] and psi of A's
-// rows [-3, n + 2].  Both steps call the same routines as the single-step
-// walk, in the same order, so the result is bitwise that of two single steps.
+// the loaded rows; step B (time t + 1) pulls A's post-collision values from
+// LDS.  The update of a cell depends on the cells within two of it, so B's
+// output strip is narrower than A's by three columns on each side (A's force
+// needs psi one column beyond, B pulls one column beyond A's valid results,
+// and B's force needs psi one column beyond that), and B's output rows
+// [0, n) need A's rows [-2, n + 1] and psi of A's rows [-3, n + 2].  Both
+// steps call the same routines as the single-step walk, in the same order, on
+// the same values (A's results rounded to the storage type, as a single step
+// stores them), so the result is bitwise that of two single steps.
 //
-// The walk runs m = 0 .. n + 5; at iteration m it prefetches A's populations
-// of row m - 3 + PF, turns row m - 3 into psi, collides A's row m - 4 into the
-// ring, pulls B's row m - 5 from the ring and turns it into psi, and collides
-// and stores B's row m - 6.  Register sets rotate with period 6 (the loop is
-// unrolled six times).
+// The walk runs m = 0 .. n + 5; iteration m
+//   prefetches A's populations of row m - 2,
+//   turns A's row m - 3 into rho and psi (psi to LDS; barrier 1),
+//   collides A's row m - 4 and hands it to B (barrier 2),
+//   pulls B's row m - 5 and turns it into rho and psi (psi to LDS; barrier 3),
+//   pulls B's row m - 6 again, collides it and stores it.
+// psi rows live in LDS rings of three rows (slot = iteration mod 3); the
+// force reads its 3 x 3 window there.  Of A's post-collision values only the
+// populations that B pulls from a neighbouring lane go through LDS, each kept
+// as long as B reads it: 7 and 8 (pulled from row r + 1) two iterations, 1 and
+// 3 (row r) three, 5 and 6 (row r - 1) four.  Populations 0, 2 and 4 come
+// from the own lane and stay in registers.  Register sets rotate with period 6
+// (the loop is unrolled six times).
+template <class R, int BX>
+struct Pass2Lds {
+    R psi_a[3][BX], psi_b[3][BX];  // psi of A's and B's rows
+    R p78[2][2][BX];               // populations 7, 8 of A's rows
+    R p13[3][2][BX];               // populations 1, 3
+    R p56[4][2][BX];               // populations 5, 6
+};
+
 template <int BX, int PF, int FORCE, int ST, int COLL>
 __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ src,
                                       typename Store<ST>::E *__restrict__ dst, const Coeffs &c,
                                       long long t, int ys, int n, int x, const Cols &cols,
                                       bool active, bool valid_b, bool interior,
-                                      typename Store<ST>::R *lds_a, typename Store<ST>::R *lds_b,
-                                      typename Store<ST>::R *ring, unsigned long long &bad)
+                                      Pass2Lds<typename Store<ST>::R, BX> &L,
+                                      unsigned long long &bad)
 {
     using E = typename Store<ST>::E;
     using R = typename Store<ST>::R;
@@ -872,104 +889,130 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     auto check = [&](bool ok, long long step, int s) {
         if (!ok) bad = min(bad, domain_key(step, lrow(s), x, c.nx));
     };
+    // psi window row of slot s of a ring
+    auto psi_row = [&](const R(*ring)[BX], int s) {
+        return Row<R>{ring[s][txm], ring[s][tx], ring[s][txp], R(0)};
+    };
 
-    R fa[K][kQ], fb[2][kQ];
-    Row<R> pa[3], pb[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        pa[k] = pb[k] = Row<R>{R(0), R(0), R(0), R(0)};
+    R fa[K][kQ];
+    R rho_a[2], rho_b[2];   // rho of the last two psi rows of each step
+    R h0[3], h2[6], h4[2];  // populations 0, 2, 4 of A's last post-collision rows
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
             fa[k][i] = R(0);
-        fb[0][i] = fb[1][i] = R(0);
     }
+    rho_a[0] = rho_a[1] = rho_b[0] = rho_b[1] = R(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        h2[k] = R(0);
+    h0[0] = h0[1] = h0[2] = h4[0] = h4[1] = R(0);
     // prologue: A's populations of rows -3 .. -4 + PF
 #pragma unroll
     for (int p = 0; p < PF; ++p)
         load_pulled<ST>(src, c, lrow(-3 + p), cols, fa[(1 + p) % K]);
 
-    auto body = [&](auto Jc, int m) {
+    // gates: the first iterations skip the work on rows no output needs (A's
+    // collision of rows -4, -3, B's psi of rows -5 .. -2, B's collision of
+    // rows -6 .. -1); FIRST marks an iteration of the peeled first six
+    auto body = [&](auto Jc, auto firstc, int m) {
         constexpr int J = decltype(Jc)::value;  // m % 6
+        constexpr bool FIRST = decltype(firstc)::value;
+        constexpr bool DO_A = !FIRST || J >= 2, DO_BPSI = !FIRST || J >= 4, DO_BCOL = !FIRST;
         constexpr int a_cur = J % K, a_lead = (J + 1) % K, a_fetch = (J + 1 + PF) % K;
         {
             const int s = m - 3 + PF;
             load_pulled<ST>(src, c, lrow(s < n + 2 ? s : n + 2), cols, fa[a_fetch]);
         }
-        // step A: psi of row m - 3 (always one of A's rows -3 .. n + 2)
-        Row<R> &LA = pa[(J + 2) % 3];
+        // step A: rho and psi of row m - 3 (always one of A's rows -3 .. n + 2)
         {
-            const bool ok = rho_psi<FORCE, R>(fa[a_lead], gref, P, LA.rho, LA.o);
+            R psi;
+            const bool ok = rho_psi<FORCE, R>(fa[a_lead], gref, P, rho_a[J % 2], psi);
             if (active) check(ok, t, m - 3);
-            R *buf = lds_a + (m & 1) * BX;
-            buf[tx] = LA.o;
+            L.psi_a[J % 3][tx] = psi;
             __syncthreads();
-            LA.l = buf[txm];
-            LA.r = buf[txp];
         }
-        // step A: collision of row m - 4 into the ring
-        {
-            const Row<R> &TA = pa[J % 3], &CA = pa[(J + 1) % 3];
+        // step A: collision of row m - 4; B's share of it to LDS and registers
+        if constexpr (DO_A) {
             R Fx = R(0), Fy = R(0);
             if (FORCE) {
+                const Row<R> T = psi_row(L.psi_a, (J + 1) % 3);
+                const Row<R> C = psi_row(L.psi_a, (J + 2) % 3);
+                const Row<R> U = psi_row(L.psi_a, J % 3);
                 R sv[kQ];
-                stencil<+1, R>(TA, CA, LA, sv);
+                stencil<+1, R>(T, C, U, sv);
                 force<R>(sv, P, Fx, Fy);
             }
+            R *g = fa[a_cur];
+            const R rho = rho_a[(J + 1) % 2];
             R ux, uy;
-            velocity<R>(fa[a_cur], CA.rho, Fx, Fy, ux, uy);
+            velocity<R>(g, rho, Fx, Fy, ux, uy);
             if constexpr (COLL == LBM_COLL_MRT)
-                collide_mrt<R>(fa[a_cur], CA.rho, ux, uy, Fx, Fy, P);
+                collide_mrt<R>(g, rho, ux, uy, Fx, Fy, P);
             else
-                collide<R>(fa[a_cur], gref, CA.rho, ux, uy, Fx, Fy, P);
+                collide<R>(g, gref, rho, ux, uy, Fx, Fy, P);
             // rounded to the storage type, as a single step stores them
-            R *w = ring + ((J + 2) % 3) * kQ * BX;
-#pragma unroll
-            for (int i = 0; i < kQ; ++i)
-                w[i * BX + tx] = (R)(E)fa[a_cur][i];
-            __syncthreads();
+            auto rd = [&](int i) { return (R)(E)g[i]; };
+            h0[J % 3] = rd(0);
+            h2[J] = rd(2);
+            h4[J % 2] = rd(4);
+            L.p13[J % 3][0][tx] = rd(1);
+            L.p13[J % 3][1][tx] = rd(3);
+            L.p56[m & 3][0][tx] = rd(5);
+            L.p56[m & 3][1][tx] = rd(6);
+            L.p78[J % 2][0][tx] = rd(7);
+            L.p78[J % 2][1][tx] = rd(8);
         }
-        // step B: pull row m - 5 from A's rows m - 6, m - 5, m - 4, and its psi
-        Row<R> &LB = pb[(J + 2) % 3];
-        {
-            const R *rm = ring + (J % 3) * kQ * BX;        // lattice row r - 1
-            const R *rc = ring + ((J + 1) % 3) * kQ * BX;  // row r
-            const R *rp = ring + ((J + 2) % 3) * kQ * BX;  // row r + 1
-            R *g = fb[(J + 1) % 2];
-            g[0] = rc[0 * BX + tx];
-            g[1] = rc[1 * BX + txm];
-            g[2] = rm[2 * BX + tx];
-            g[3] = rc[3 * BX + txp];
-            g[4] = rp[4 * BX + tx];
-            g[5] = rm[5 * BX + txm];
-            g[6] = rm[6 * BX + txp];
-            g[7] = rp[7 * BX + txp];
-            g[8] = rp[8 * BX + txm];
-            const bool ok = rho_psi<FORCE, R>(g, gref, P, LB.rho, LB.o);
+        __syncthreads();
+        // B's pulled populations of row m - 5 - back (back = 0: the row turned
+        // into psi now, back = 1: the row collided now); A's row q was written
+        // at iteration q + 4
+        auto pull_b = [&](auto backc, R g[kQ]) {
+            constexpr int b = decltype(backc)::value;
+            constexpr int s2 = (J + 2 - b) % 2, s3r = (J + 5 - b) % 3, s6 = (J + 10 - b) % 6;
+            const int s4 = (m + 2 - b) & 3;
+            // row r + 1 (written at m - b), row r (m - 1 - b), row r - 1 (m - 2 - b)
+            g[4] = h4[s2];
+            g[7] = L.p78[s2][0][txp];
+            g[8] = L.p78[s2][1][txm];
+            g[0] = h0[s3r];
+            g[1] = L.p13[s3r][0][txm];
+            g[3] = L.p13[s3r][1][txp];
+            g[2] = h2[s6];
+            g[5] = L.p56[s4][0][txm];
+            g[6] = L.p56[s4][1][txp];
+        };
+        // step B: rho and psi of row m - 5
+        if constexpr (DO_BPSI) {
+            R g[kQ];
+            pull_b(std::integral_constant<int, 0>{}, g);
+            R psi;
+            const bool ok = rho_psi<FORCE, R>(g, gref, P, rho_b[J % 2], psi);
             if (valid_b && m - 5 >= -1) check(ok, t + 1, m - 5);
-            R *buf = lds_b + (m & 1) * BX;
-            buf[tx] = LB.o;
-            __syncthreads();
-            LB.l = buf[txm];
-            LB.r = buf[txp];
+            L.psi_b[J % 3][tx] = psi;
         }
+        __syncthreads();
         // step B: collision of row m - 6 and its store
-        {
-            const Row<R> &TB = pb[J % 3], &CB = pb[(J + 1) % 3];
-            R *g = fb[J % 2];
+        if constexpr (DO_BCOL) {
+            R g[kQ];
+            pull_b(std::integral_constant<int, 1>{}, g);
             R Fx = R(0), Fy = R(0);
             if (FORCE) {
+                const Row<R> T = psi_row(L.psi_b, (J + 1) % 3);
+                const Row<R> C = psi_row(L.psi_b, (J + 2) % 3);
+                const Row<R> U = psi_row(L.psi_b, J % 3);
                 R sv[kQ];
-                stencil<+1, R>(TB, CB, LB, sv);
+                stencil<+1, R>(T, C, U, sv);
                 force<R>(sv, P, Fx, Fy);
             }
+            const R rho = rho_b[(J + 1) % 2];
             R ux, uy;
-            velocity<R>(g, CB.rho, Fx, Fy, ux, uy);
+            velocity<R>(g, rho, Fx, Fy, ux, uy);
             if constexpr (COLL == LBM_COLL_MRT)
-                collide_mrt<R>(g, CB.rho, ux, uy, Fx, Fy, P);
+                collide_mrt<R>(g, rho, ux, uy, Fx, Fy, P);
             else
-                collide<R>(g, gref, CB.rho, ux, uy, Fx, Fy, P);
+                collide<R>(g, gref, rho, ux, uy, Fx, Fy, P);
             const int sb = m - 6;
             if (interior && sb >= 0 && sb < n) {
                 const size_t prow = (size_t)lrow(sb) * c.pitch;
@@ -982,29 +1025,40 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     };
 
     constexpr int U = 6;
-    const int total = n + 6;
-    int m = 0;
+    const int total = n + 6;  // >= 7
+    using First = std::true_type;
+    using Rest = std::false_type;
+    unroll([&](auto J) { body(J, First{}, decltype(J)::value); },
+           std::make_integer_sequence<int, U>{});
+    int m = U;
     for (; m + U <= total; m += U)
-        unroll([&](auto J) { body(J, m + decltype(J)::value); },
+        unroll([&](auto J) { body(J, Rest{}, m + decltype(J)::value); },
                std::make_integer_sequence<int, U>{});
     unroll([&](auto J) {
-        if (m + decltype(J)::value < total) body(J, m + decltype(J)::value);
+        if (m + decltype(J)::value < total) body(J, Rest{}, m + decltype(J)::value);
     }, std::make_integer_sequence<int, U - 1>{});
 }
 
 // Halo columns of the two-step pass on each side of its output strip.
 constexpr int kHalo2 = 3;
 
+// Waves per SIMD the two-step pass is compiled for.  FP64 runs at two (173
+// VGPRs with BGK; bounding it to three waves spilled 8 registers and measured
+// 2-4% slower); the FP32-arithmetic modes fit four.
+template <int ST, int COLL>
+constexpr int kWaves2 = ST == LBM_STORE_F64 ? 2 : 4;
+
 // One tile of the two-step pass: output strip `strip` of row band `seg`.
 template <int BX, int PF, int FORCE, int ST, int COLL>
-__global__ __launch_bounds__(BX) void sweep2_kernel(const void *__restrict__ src_v,
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST, COLL>)))
+void sweep2_kernel(const void *__restrict__ src_v,
                                                     void *__restrict__ dst_v, Coeffs c, Tiles tl,
                                                     long long t,
                                                     unsigned long long *__restrict__ err)
 {
     using E = typename Store<ST>::E;
     using R = typename Store<ST>::R;
-    __shared__ R lds_a[2 * BX], lds_b[2 * BX], ring[3 * kQ * BX];
+    __shared__ Pass2Lds<R, BX> lds;
     const int tile = xcd_tile(blockIdx.x, tl.ntiles);
     const int seg = tile / tl.nstrips;
     const int strip = tile - seg * tl.nstrips;
@@ -1024,7 +1078,7 @@ __global__ __launch_bounds__(BX) void sweep2_kernel(const void *__restrict__ src
     const Cols cols{(uint32_t)x * es, (uint32_t)xm * es, (uint32_t)xp * es};
     unsigned long long bad = ~0ull;
     walk2<BX, PF, FORCE, ST, COLL>((const E *)src_v, (E *)dst_v, c, t, ys, ye - ys, x, cols, active,
-                                   valid_b, interior, lds_a, lds_b, ring, bad);
+                                   valid_b, interior, lds, bad);
     if (bad != ~0ull) atomicMin(err, bad);
 }
 
@@ -1183,6 +1237,7 @@ struct lbm_handle {
     int bx, seg_rows;
     Tiles tiles;
     int fuse;                // time steps per pass of the step kernel (1 or 2)
+    int cus;                 // compute units of the device (default shapes)
     int bx2, seg_rows2;      // launch shape of the two-step pass
     Tiles tiles2;
     lbm_status sticky;
@@ -1389,23 +1444,59 @@ void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
     *rows_out = rows;
 }
 
-// Default shape of the two-step pass: 256 threads, 16-row segments.  Measured
-// on 2048 x 2048 over 128..512 threads and 8..32 rows: FP64 and FP16 are
-// fastest at (256, 16..20), FP32 at (256, 12..20); 512 threads (one
-// workgroup per CU) are clearly slower.
-constexpr int kFuseBx = 256, kFuseRows = 16;
+// Default shape of the two-step pass: 256 threads, and as many row segments
+// as fill whole rounds of the workgroups the chip runs at once.  A workgroup
+// walks its segment from start to end, so the launch takes as many rounds as
+// it has tiles per concurrent slot, each about as long as a segment; a
+// round that is only partly filled costs as much as a full one.  Slots per CU
+// as measured best (FP64: two workgroups of 256 threads, VGPR-bound; FP32:
+// two; FP16: four), segments of at least kMinRows2 rows (the six extra rows
+// of each segment are overhead) and at most kMaxRows2 (beyond that nothing is
+// gained on large lattices).  Measured on 2048^2: FP64 (256, 37) 67 us/step
+// against 72-89 for shapes that leave a partial round; 8192^2: 32..64 rows
+// within 1%.
+constexpr int kFuseBx = 256;
 
-// Default segment length of the two-step pass: kFuseRows, or longer where the
-// lattice would need more than kMaxTiles workgroups.  False if no length fits.
-bool default_rows2(int nx, int ny, int storage, int bx, int *rows, Tiles *tl)
+int slots_per_cu2(int storage, int bx)
 {
-    for (int r = std::min(kFuseRows, ny);; r = std::min(2 * r, ny)) {
+    const int per256 = storage == LBM_STORE_F16_SHIFTED ? 4 : 2;
+    return std::max(1, per256 * 256 / bx);
+}
+
+// Segment length of the default two-step shape for block width bx on a chip
+// with `cus` compute units.  False if no length fits kMaxTiles.
+bool default_rows2(int nx, int ny, int storage, int bx, int cus, int *rows, Tiles *tl)
+{
+    const int min_rows = storage == LBM_STORE_F16_SHIFTED ? 12 : 24;
+    const int max_rows = 40;
+    Tiles t0;
+    if (!make_tiles2(nx, ny, bx, ny, strip_align(storage), &t0)) return false;
+    const long long slots = (long long)slots_per_cu2(storage, bx) * cus;
+    const long long per_round = std::max(1ll, slots / t0.nstrips);  // segments per round
+    long long nseg = per_round;
+    if ((ny + nseg - 1) / nseg > max_rows)  // whole rounds of segments of <= max_rows
+        nseg = per_round * ((ny + per_round * max_rows - 1) / (per_round * max_rows));
+    if ((ny + nseg - 1) / nseg < min_rows)  // small lattices: fewer, longer segments
+        nseg = (ny + min_rows - 1) / min_rows;
+    nseg = std::max(1ll, std::min<long long>(nseg, ny));
+    for (int r = (int)((ny + nseg - 1) / nseg);; r = std::min(2 * r, ny)) {
         if (make_tiles2(nx, ny, bx, r, strip_align(storage), tl)) {
             *rows = r;
             return true;
         }
         if (r == ny) return false;
     }
+}
+
+// Compute units of the current device (256 on MI355X if the query fails).
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        return 256;
+    return cus;
 }
 
 lbm_status dev_fail(lbm_handle *h, hipError_t e, const char *what)
@@ -1804,9 +1895,10 @@ lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspac
         return LBM_ERR_INVALID_ARG;
     }
     // two steps per pass wherever the storage mode has the two-step kernel
+    h->cus = device_cus();
     h->bx2 = kFuseBx;
     h->fuse = params->storage != LBM_STORE_F16_LOCAL &&
-                      default_rows2(params->nx, params->ny, params->storage, h->bx2,
+                      default_rows2(params->nx, params->ny, params->storage, h->bx2, h->cus,
                                     &h->seg_rows2, &h->tiles2)
                   ? 2
                   : 1;
@@ -1949,7 +2041,7 @@ lbm_status lbm_set_fusion(lbm_handle *h, int32_t steps, int32_t block_x, int32_t
     }
     int rows = seg_rows;
     Tiles tl;
-    if (rows == 0 ? !default_rows2(h->p.nx, h->p.ny, h->p.storage, bx, &rows, &tl)
+    if (rows == 0 ? !default_rows2(h->p.nx, h->p.ny, h->p.storage, bx, h->cus, &rows, &tl)
                   : !make_tiles2(h->p.nx, h->p.ny, bx, rows, strip_align(h->p.storage), &tl)) {
         h->last_error = "launch shape needs too many workgroups";
         return LBM_ERR_INVALID_ARG;

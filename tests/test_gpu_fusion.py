@@ -94,11 +94,13 @@ def test_fp64_two_step_pass_matches_oracle(oracle):
 def test_defaults_and_rejected_arguments():
     require_gpu()
     from paper_2003_07968_amd import lbm
-    for storage in ("f64", "f32", "f16"):
+    # default shape on a small lattice: one strip, segments of the minimum
+    # length (24 rows; 12 with FP16 storage)
+    for storage, rows in (("f64", 24), ("f32", 24), ("f16", 12)):
         p, rho0 = _smooth_case(64, 48, storage)
         lat = gpu_lattice(p, rho0)
         assert lat.fusion() == 2
-        assert lat.launch()[:2] == (256, 16)
+        assert lat.launch() == (256, rows, 48 // rows), storage
     p, rho0 = _smooth_case(64, 48, "f16l")
     lat = gpu_lattice(p, rho0)
     assert lat.fusion() == 1
@@ -111,7 +113,7 @@ def test_defaults_and_rejected_arguments():
         with pytest.raises(lbm.LbmError) as e:
             lat.set_fusion(*bad)
         assert e.value.status == lbm.LBM_ERR_INVALID_ARG, bad
-    assert lat.fusion() == 2 and lat.launch()[:2] == (256, 16)
+    assert lat.fusion() == 2 and lat.launch()[:2] == (256, 24)
     lat.set_fusion(1)
     assert lat.fusion() == 1
 
