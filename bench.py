@@ -119,9 +119,11 @@ def cpu_baseline(budget_s=12.0):
 def run_batch(args):
     """256 independent droplet lattices (sides log-uniform in [64, 512], T_r
     U[0.55, 0.95], sigma U[1/8, 4], R0 U[0.15, 0.35] side, seed 6) stepped by
-    one batched launch per step with FP32-shifted storage, shape chosen by the
-    autotuner, 8-step HIP graphs replayed.  Beside it, the same lattices in
-    FP64 stepped one launch per lattice per step (the plain path)."""
+    one batched launch per two steps (the two-step pass; per step with
+    --storage f16l) with FP32-shifted storage, shape chosen by the autotuner,
+    8-step HIP graphs replayed.  Beside it, the same lattices in FP64 stepped
+    each on its own (the plain path: one two-step launch per lattice per two
+    steps)."""
     import torch
     from paper_2003_07968_amd import lbm
     from paper_2003_07968_amd import workloads as W
@@ -133,8 +135,11 @@ def run_batch(args):
         cells = sum(p["nx"] * p["ny"] for p, _ in cases)
         lats = [lbm.Lattice(p, r) for p, r in cases]
         batch = lbm.Batch(len(lats))
+        if args.fusion is not None:
+            batch.set_fusion(args.fusion)
         for lat in lats:
             batch.add(lat)
+        fusion = batch.fusion()
         bx, rows, us = batch.autotune()
         err(f"batch of {len(lats)} lattices, {cells} cells; autotuned block {bx}, "
             f"rows {rows}: {us:.1f} us/step")
@@ -151,9 +156,9 @@ def run_batch(args):
             lat.sync()
         err(f"timed {args.steps} batched steps: {gpu_ms:.2f} ms")
 
-        # the plain path on the same lattices: FP64 storage, one launch per
-        # lattice per step
-        seq_steps = max(8, args.steps // 10)
+        # the plain path on the same lattices: FP64 storage, each lattice on
+        # its own (two steps per launch)
+        seq_steps = 2 * max(4, args.steps // 20)
         plain = []
         for p, r in cases:
             q = dict(p)
@@ -165,9 +170,9 @@ def run_batch(args):
         e2 = torch.cuda.Event(enable_timing=True)
         e3 = torch.cuda.Event(enable_timing=True)
         e2.record(stream)
-        for _ in range(seq_steps):
+        for _ in range(seq_steps // 2):
             for lat in plain:
-                lat.step(1)
+                lat.step(2)
         e3.record(stream)
         torch.cuda.synchronize()
         plain_ms = e2.elapsed_time(e3)
@@ -177,7 +182,9 @@ def run_batch(args):
     plain_mlups = cells * seq_steps / (plain_ms / 1e3) / 1e6
     bpc = BYTES_PER_CELL[storage]
     step_ms = gpu_ms / args.steps
-    achieved = bpc * cells / (step_ms / 1e3) / 1e9
+    launches = args.steps // fusion + args.steps % fusion
+    launch_ms = gpu_ms / launches
+    achieved = bpc * cells / (launch_ms / 1e3) / 1e9
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 5),
@@ -189,15 +196,19 @@ def run_batch(args):
         "config": {
             "workload": "batch of 256 D2Q9 droplet lattices, sides log-uniform [64, 512], "
                         "T_r U[0.55,0.95], sigma U[1/8,4], R0 U[0.15,0.35] side, seed 6; "
-                        "one batched launch per step, 8-step HIP graphs, autotuned shape",
+                        "one batched launch per two steps (per step for f16l), 8-step HIP "
+                        "graphs, autotuned shape",
             "storage": storage, "lattices": len(lats), "cells": cells,
-            "bytes_per_cell_update": bpc, "launch_block_x_seg_rows": [bx, rows],
+            "steps_per_launch": fusion, "bytes_per_cell_and_launch": bpc,
+            "launch_block_x_seg_rows": [bx, rows],
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "batch_step_kernel (plus a one-thread counter bump per step)",
-            "kernel_avg_ms": round(step_ms, 5),
+            "kernel": ("batch2_kernel (two steps per launch" if fusion == 2 else
+                       "batch_step_kernel (one step per launch") +
+                      ", plus a one-thread counter bump per launch)",
+            "kernel_avg_ms": round(launch_ms, 5),
         },
         "plain_fp64_sequential": {
             "value": round(plain_mlups, 1), "unit": "MLUPS", "steps": seq_steps,

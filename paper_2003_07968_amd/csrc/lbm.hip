@@ -15,7 +15,7 @@
 // from w_i R(z) with a per-cell FP32 reference R (the nine values a cell sends
 // share its R).  The diagnostics reductions are FP64 in every mode.
 //
-// Kernel design (one fused pass per step, HBM-bound):
+// Kernel design (one fused pass per step, or per two steps):
 //   * populations are arrays X_i[y][x] holding the post-collision values of
 //     the previous step; the pulled value is f_i(x) = X_i(x - c_i), so every
 //     row is read with unit stride (shifted by at most one element) and
@@ -23,17 +23,22 @@
 //     stored one after another (row-interleaved), so that a row step reads
 //     and writes three neighbouring blocks of memory instead of nine regions
 //     a whole plane apart;
-//   * a workgroup of BX threads owns a strip of BX - 2 interior columns plus
-//     one halo column on each side, and walks a segment of rows.  At each row
-//     it loads the pulled populations of the row ahead, turns them into rho
-//     and psi, exchanges psi with its x-neighbours through one double-buffered
-//     LDS row, and keeps the 3x3 psi window of its own column in registers;
+//   * single step: a workgroup of BX threads owns a strip of interior columns
+//     (BX - 2, rounded down to a multiple of 128 bytes) plus one halo column
+//     on each side, and walks a segment of rows.  At each row it loads the
+//     pulled populations of the row ahead, turns them into rho and psi,
+//     exchanges psi with its x-neighbours through one double-buffered LDS
+//     row, and keeps the 3x3 psi window of its own column in registers;
 //     populations are prefetched one further row ahead.  Each population is
-//     read from HBM once per step, apart from the two halo columns per strip
-//     and the two halo rows per segment, which are re-read through L2;
-//   * neighbouring segments walk in opposite directions, so both workgroups
-//     of a segment boundary touch its rows at about the same time and the
-//     second reads them from L2.
+//     read from HBM once per step, apart from the halo columns and rows,
+//     which are re-read through L2; neighbouring segments walk in opposite
+//     directions, so both workgroups of a segment boundary touch its rows at
+//     about the same time;
+//   * two steps per pass (the default): the first step is computed on a tile
+//     widened by three columns and rows on each side and handed to the
+//     second through LDS, so the populations are read and written once per
+//     two updates (walk2 below);
+//   * workgroups take their tiles in an XCD-aware order (xcd_tile).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -801,33 +806,42 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void sweep_kernel(const 
 // One lattice of a batch, as the batched step kernel sees it.
 struct BatchEntry {
     Coeffs c;
-    Tiles tl;
-    const void *buf[2];       // population buffers; the first batched step reads buf[0]
+    Tiles tl, tl2;            // tiles of a single step and of the two-step pass
+    const void *buf[2];       // population buffers; the first batched launch reads buf[0]
     unsigned long long *err;  // the lattice's sticky error word
     long long t0;             // the lattice's step count before the batched steps
-    int tile0;                // its first tile in the batch grid
+    int tile0, tile0_2;       // its first tile in the single-step / two-step batch grid
 };
 
+// Lattice of batch tile b: the last entry whose first tile (member F) is <= b
+// (binary search over the table, uniform per workgroup).
+template <int BatchEntry::*F>
+__device__ __forceinline__ const BatchEntry &batch_entry(const BatchEntry *__restrict__ table,
+                                                         int nlat, int b)
+{
+    int lo = 0, hi = nlat - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].*F <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return table[lo];
+}
+
 // One time step of every lattice of a batch: workgroup b takes batch tile
-// xcd_tile(b) and runs tile b - tile0 of the lattice whose tile range holds
-// it (binary search over the table, uniform per workgroup).  The step count since the table was written
-// is read from d_steps (so that a captured graph replays correctly); its
-// parity selects the source buffer.
+// xcd_tile(b) and runs tile b - tile0 of its lattice.  The steps and the
+// launches since the table was written are read from d_ctr[0] and d_ctr[1]
+// (so that a captured graph replays correctly): the first gives the time,
+// the parity of the second the source buffer.
 template <int BX, int PF, int FORCE, int ST, int COLL>
 __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(const BatchEntry *__restrict__ table,
                                                         int nlat,
-                                                        const long long *__restrict__ d_steps)
+                                                        const long long *__restrict__ d_ctr)
 {
-    const long long steps = *d_steps;
-    const int parity = (int)(steps & 1);
-    int lo = 0, hi = nlat - 1;
+    const long long steps = d_ctr[0];
+    const int parity = (int)(d_ctr[1] & 1);
     const int b = xcd_tile(blockIdx.x, gridDim.x);
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (table[mid].tile0 <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatchEntry &e = table[lo];
+    const BatchEntry &e = batch_entry<&BatchEntry::tile0>(table, nlat, b);
     sweep_tile<BX, kStep, PF, FORCE, ST, COLL>(e.buf[parity], (void *)e.buf[parity ^ 1], e.c,
                                                e.tl, b - e.tile0, e.t0 + steps, e.err, Fields{},
                                                nullptr, nullptr);
@@ -1050,16 +1064,14 @@ constexpr int kWaves2 = ST == LBM_STORE_F64 ? 2 : 4;
 
 // One tile of the two-step pass: output strip `strip` of row band `seg`.
 template <int BX, int PF, int FORCE, int ST, int COLL>
-__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST, COLL>)))
-void sweep2_kernel(const void *__restrict__ src_v,
-                                                    void *__restrict__ dst_v, Coeffs c, Tiles tl,
-                                                    long long t,
-                                                    unsigned long long *__restrict__ err)
+__device__ __forceinline__ void sweep2_tile(const void *__restrict__ src_v,
+                                            void *__restrict__ dst_v, const Coeffs &c,
+                                            const Tiles &tl, int tile, long long t,
+                                            unsigned long long *__restrict__ err)
 {
     using E = typename Store<ST>::E;
     using R = typename Store<ST>::R;
     __shared__ Pass2Lds<R, BX> lds;
-    const int tile = xcd_tile(blockIdx.x, tl.ntiles);
     const int seg = tile / tl.nstrips;
     const int strip = tile - seg * tl.nstrips;
     const int xs = strip * tl.width;
@@ -1082,8 +1094,41 @@ void sweep2_kernel(const void *__restrict__ src_v,
     if (bad != ~0ull) atomicMin(err, bad);
 }
 
-__global__ void bump_counter(long long *p) { *p += 1; }
-__global__ void set_counter(long long *p, long long v) { *p = v; }
+// The two-step pass over one lattice.
+template <int BX, int PF, int FORCE, int ST, int COLL>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST, COLL>)))
+void sweep2_kernel(const void *__restrict__ src, void *__restrict__ dst, Coeffs c, Tiles tl,
+                   long long t, unsigned long long *__restrict__ err)
+{
+    sweep2_tile<BX, PF, FORCE, ST, COLL>(src, dst, c, tl, xcd_tile(blockIdx.x, tl.ntiles), t, err);
+}
+
+// The two-step pass over every lattice of a batch (tiles and counters as in
+// batch_step_kernel; a launch advances two steps and swaps the buffers once).
+template <int BX, int PF, int FORCE, int ST, int COLL>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST, COLL>)))
+void batch2_kernel(const BatchEntry *__restrict__ table, int nlat,
+                   const long long *__restrict__ d_ctr)
+{
+    const long long steps = d_ctr[0];
+    const int parity = (int)(d_ctr[1] & 1);
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const BatchEntry &e = batch_entry<&BatchEntry::tile0_2>(table, nlat, b);
+    sweep2_tile<BX, PF, FORCE, ST, COLL>(e.buf[parity], (void *)e.buf[parity ^ 1], e.c, e.tl2,
+                                         b - e.tile0_2, e.t0 + steps, e.err);
+}
+
+// Batch counters: p[0] steps, p[1] launches since the table was written.
+__global__ void bump_counter(long long *p, long long steps)
+{
+    p[0] += steps;
+    p[1] += 1;
+}
+__global__ void clear_counters(long long *p)
+{
+    p[0] = 0;
+    p[1] = 0;
+}
 
 // Second stage of the diagnostics: one workgroup sums the per-tile partials
 // in a fixed order.
@@ -1248,16 +1293,19 @@ struct lbm_batch {
     int capacity;
     hipStream_t stream;
     BatchEntry *d_table;
-    long long *d_steps;       // steps since the table was written
+    long long *d_ctr;         // steps and launches since the table was written
     std::vector<lbm_handle *> members;
     std::vector<BatchEntry> h_table;
     std::vector<int64_t> t_at_upload;
     std::vector<void *> cur_at_upload, nxt_at_upload;
-    long long steps_since_upload;
+    long long steps_since_upload, launches_since_upload;
     bool table_valid;
     int storage, force_on, coll;
-    int bx, rows;
-    int total_tiles;
+    int fuse_max;             // steps per launch requested (1 or 2)
+    int bx, rows;             // single-step shape
+    int bx2, rows2;           // two-step shape
+    bool auto_rows2;          // rows2 chosen at each upload (until autotuned)
+    int total_tiles, total_tiles2;
     hipGraphExec_t graph;     // kGraphSteps batched steps, valid with the table
     bool graph_valid;
     std::string last_error;
@@ -1265,7 +1313,9 @@ struct lbm_batch {
 
 namespace {
 
-constexpr int kGraphSteps = 8;
+constexpr int kGraphSteps = 8;    // even: a multiple of the steps per launch
+constexpr int kBatchRows2 = 24;   // segment rows of the two-step pass in a batch
+const int kBatchRowsCand2[] = {2, 3, 4, 6, 8, 12, 16, 20, 24, 32, 40};
 
 struct Layout {
     size_t err, diag_out, partials, rho_snap, bufA, bufB, total, plane, pitch;
@@ -1447,14 +1497,16 @@ void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
 // Default shape of the two-step pass: 256 threads, and as many row segments
 // as fill whole rounds of the workgroups the chip runs at once.  A workgroup
 // walks its segment from start to end, so the launch takes as many rounds as
-// it has tiles per concurrent slot, each about as long as a segment; a
-// round that is only partly filled costs as much as a full one.  Slots per CU
-// as measured best (FP64: two workgroups of 256 threads, VGPR-bound; FP32:
-// two; FP16: four), segments of at least kMinRows2 rows (the six extra rows
-// of each segment are overhead) and at most kMaxRows2 (beyond that nothing is
-// gained on large lattices).  Measured on 2048^2: FP64 (256, 37) 67 us/step
-// against 72-89 for shapes that leave a partial round; 8192^2: 32..64 rows
-// within 1%.
+// it has tiles per concurrent slot, each about as long as a segment; a round
+// that is only partly filled costs as much as a full one.  Slots per CU as
+// measured best (FP64: two workgroups of 256 threads, VGPR-bound; FP32: two;
+// FP16: four).  Segments have 2 to 40 rows: lattices too small to fill one
+// round at 40 rows get one round of shorter segments (a lone workgroup is
+// latency-bound, about 0.85 us per row), larger ones whole rounds of segments
+// of up to 40 rows (longer ones gain nothing).  Measured, us per step, FP64:
+// 2048^2 (256, 37) 67 against 72-89 for shapes that leave a partial round;
+// 1024^2 11 rows 22.8 against 27.7 at 24; 64^2 2 rows 5.8 against 9.1 with
+// single steps; 8192^2 32..64 rows within 1%.
 constexpr int kFuseBx = 256;
 
 int slots_per_cu2(int storage, int bx)
@@ -1467,8 +1519,7 @@ int slots_per_cu2(int storage, int bx)
 // with `cus` compute units.  False if no length fits kMaxTiles.
 bool default_rows2(int nx, int ny, int storage, int bx, int cus, int *rows, Tiles *tl)
 {
-    const int min_rows = storage == LBM_STORE_F16_SHIFTED ? 12 : 24;
-    const int max_rows = 40;
+    const int min_rows = 2, max_rows = 40;
     Tiles t0;
     if (!make_tiles2(nx, ny, bx, ny, strip_align(storage), &t0)) return false;
     const long long slots = (long long)slots_per_cu2(storage, bx) * cus;
@@ -1476,8 +1527,7 @@ bool default_rows2(int nx, int ny, int storage, int bx, int cus, int *rows, Tile
     long long nseg = per_round;
     if ((ny + nseg - 1) / nseg > max_rows)  // whole rounds of segments of <= max_rows
         nseg = per_round * ((ny + per_round * max_rows - 1) / (per_round * max_rows));
-    if ((ny + nseg - 1) / nseg < min_rows)  // small lattices: fewer, longer segments
-        nseg = (ny + min_rows - 1) / min_rows;
+    if ((ny + nseg - 1) / nseg < min_rows) nseg = (ny + min_rows - 1) / min_rows;
     nseg = std::max(1ll, std::min<long long>(nseg, ny));
     for (int r = (int)((ny + nseg - 1) / nseg);; r = std::min(2 * r, ny)) {
         if (make_tiles2(nx, ny, bx, r, strip_align(storage), tl)) {
@@ -1688,7 +1738,7 @@ hipError_t launch_batch_t(lbm_batch *b)
 #define LBM_CASE(BX)                                                                          \
     case BX:                                                                                  \
         hipLaunchKernelGGL((batch_step_kernel<BX, kPrefetch, FORCE, ST, COLL>), grid, dim3(BX), \
-                           0, b->stream, b->d_table, nlat, b->d_steps);                       \
+                           0, b->stream, b->d_table, nlat, b->d_ctr);                         \
         break;
         LBM_CASE(64)
         LBM_CASE(128)
@@ -1724,10 +1774,74 @@ hipError_t launch_batch_f(lbm_batch *b)
     return hipErrorInvalidValue;
 }
 
-// One batched step (the kernel only; the caller bumps the step counter).
+// One batched step (the kernel only; the caller bumps the counters).
 hipError_t launch_batch(lbm_batch *b)
 {
     return b->force_on ? launch_batch_f<1>(b) : launch_batch_f<0>(b);
+}
+
+template <int FORCE, int ST, int COLL>
+hipError_t launch_batch2_t(lbm_batch *b)
+{
+    const dim3 grid((unsigned)b->total_tiles2);
+    const int nlat = (int)b->members.size();
+    switch (b->bx2) {
+#define LBM_CASE(BX)                                                                          \
+    case BX:                                                                                  \
+        hipLaunchKernelGGL((batch2_kernel<BX, 1, FORCE, ST, COLL>), grid, dim3(BX), 0,         \
+                           b->stream, b->d_table, nlat, b->d_ctr);                            \
+        break;
+        LBM_CASE(128)
+        LBM_CASE(256)
+        LBM_CASE(512)
+#undef LBM_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int FORCE, int ST>
+hipError_t launch_batch2_c(lbm_batch *b)
+{
+    return b->coll == LBM_COLL_MRT ? launch_batch2_t<FORCE, ST, LBM_COLL_MRT>(b)
+                                   : launch_batch2_t<FORCE, ST, LBM_COLL_BGK>(b);
+}
+
+template <int FORCE>
+hipError_t launch_batch2_f(lbm_batch *b)
+{
+    switch (b->storage) {
+    case LBM_STORE_F64: return launch_batch2_c<FORCE, LBM_STORE_F64>(b);
+    case LBM_STORE_F32_SHIFTED: return launch_batch2_c<FORCE, LBM_STORE_F32_SHIFTED>(b);
+    case LBM_STORE_F16_SHIFTED: return launch_batch2_c<FORCE, LBM_STORE_F16_SHIFTED>(b);
+    }
+    return hipErrorInvalidValue;
+}
+
+// One batched two-step launch (the kernel only).
+hipError_t launch_batch2(lbm_batch *b)
+{
+    return b->force_on ? launch_batch2_f<1>(b) : launch_batch2_f<0>(b);
+}
+
+// Steps per launch of a batch: two where its storage mode has the two-step
+// kernel and the caller has not asked for single steps.
+int batch_fuse(const lbm_batch *b)
+{
+    return b->fuse_max == 2 && b->storage != LBM_STORE_F16_LOCAL ? 2 : 1;
+}
+
+// One batched launch of `steps` (1 or 2) steps and its counter bump.
+hipError_t batch_launch_steps(lbm_batch *b, int steps)
+{
+    hipError_t e = steps == 2 ? launch_batch2(b) : launch_batch(b);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->stream, b->d_ctr,
+                           (long long)steps);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 // Average duration in microseconds of `reps` calls of fn on `stream`, after
@@ -1759,7 +1873,7 @@ double time_launches(hipStream_t stream, int reps, Fn &&fn)
 const int kTuneWidths[] = {64, 128, 192, 256, 320, 384, 512};
 const int kTuneRows[] = {3, 5, 7, 9, 13, 17};
 const int kTuneWidths2[] = {128, 256, 512};
-const int kTuneRows2[] = {8, 12, 16, 20, 24, 32};
+const int kTuneRows2[] = {12, 16, 20, 24, 32, 40, 48};
 
 // Rebuild and upload the batch table for the current members and shape.
 // Synchronous (the host staging vector is reused by the next upload).
@@ -1769,34 +1883,66 @@ lbm_status batch_upload(lbm_batch *b)
     b->t_at_upload.clear();
     b->cur_at_upload.clear();
     b->nxt_at_upload.clear();
-    int tile0 = 0;
+    int tile0 = 0, tile0_2 = 0;
     const int align = strip_align(b->storage);
+    const bool two = batch_fuse(b) == 2;
+    if (two && b->auto_rows2 && !b->members.empty()) {
+        // the segment length that minimises rounds x (rows + 6) over the whole
+        // batch, as for one lattice (the longer one on ties)
+        const long long slots =
+            (long long)slots_per_cu2(b->storage, b->bx2) * b->members[0]->cus;
+        long long best = -1;
+        for (int r : kBatchRowsCand2) {
+            long long tiles = 0;
+            bool ok = true;
+            for (const lbm_handle *h : b->members) {
+                Tiles t;
+                if (!make_tiles2(h->p.nx, h->p.ny, b->bx2, std::min(r, h->p.ny), align, &t)) {
+                    ok = false;
+                    break;
+                }
+                tiles += t.ntiles;
+            }
+            if (!ok) continue;
+            const long long cost = (tiles + slots - 1) / slots * (r + 6);
+            if (best < 0 || cost <= best) {
+                best = cost;
+                b->rows2 = r;
+            }
+        }
+    }
     for (lbm_handle *h : b->members) {
         BatchEntry e;
         e.c = h->c;
         if (!make_tiles(h->p.nx, h->p.ny, b->bx, std::min(b->rows, h->p.ny), align, &e.tl,
-                        1ll << 30)) {
+                        1ll << 30) ||
+            (two && !make_tiles2(h->p.nx, h->p.ny, b->bx2, std::min(b->rows2, h->p.ny), align,
+                                 &e.tl2))) {
             b->last_error = "launch shape does not fit a lattice of the batch";
             return LBM_ERR_INVALID_ARG;
         }
+        if (!two) e.tl2 = Tiles{0, 0, 0, 0};
         e.buf[0] = h->cur;
         e.buf[1] = h->nxt;
         e.err = h->err;
         e.t0 = h->t;
         e.tile0 = tile0;
+        e.tile0_2 = tile0_2;
         tile0 += e.tl.ntiles;
+        tile0_2 += e.tl2.ntiles;
         b->h_table.push_back(e);
         b->t_at_upload.push_back(h->t);
         b->cur_at_upload.push_back(h->cur);
         b->nxt_at_upload.push_back(h->nxt);
     }
     b->total_tiles = tile0;
+    b->total_tiles2 = tile0_2;
     hipError_t e = hipSuccess;
     if (!b->h_table.empty())
         e = hipMemcpyAsync(b->d_table, b->h_table.data(), b->h_table.size() * sizeof(BatchEntry),
                            hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(set_counter, dim3(1), dim3(1), 0, b->stream, b->d_steps, 0ll);
+        hipLaunchKernelGGL(clear_counters, dim3(1), dim3(1), 0, b->stream, b->d_ctr);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1809,6 +1955,7 @@ lbm_status batch_upload(lbm_batch *b)
         b->graph_valid = false;
     }
     b->steps_since_upload = 0;
+    b->launches_since_upload = 0;
     b->table_valid = true;
     return LBM_OK;
 }
@@ -1819,7 +1966,7 @@ lbm_status batch_upload(lbm_batch *b)
 bool batch_stale(const lbm_batch *b)
 {
     if (!b->table_valid || b->t_at_upload.size() != b->members.size()) return true;
-    const bool odd = (b->steps_since_upload & 1) != 0;
+    const bool odd = (b->launches_since_upload & 1) != 0;
     for (size_t k = 0; k < b->members.size(); ++k) {
         const lbm_handle *h = b->members[k];
         if (h->t != b->t_at_upload[k] + b->steps_since_upload) return true;
@@ -1828,20 +1975,18 @@ bool batch_stale(const lbm_batch *b)
     return false;
 }
 
-// Capture kGraphSteps batched steps (kernel + counter bump each) in a graph.
+// Capture kGraphSteps batched steps (launches of batch_fuse(b) steps, each
+// with its counter bump) in a graph.  An even number of launches, so a replay
+// leaves every lattice's state in the buffer it started from.
 hipError_t batch_capture(lbm_batch *b)
 {
     hipGraph_t g;
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
-    for (int k = 0; k < kGraphSteps && le == hipSuccess; ++k) {
-        le = launch_batch(b);
-        if (le == hipSuccess) {
-            hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->stream, b->d_steps);
-            le = hipGetLastError();
-        }
-    }
+    const int per = batch_fuse(b);
+    for (int k = 0; k < kGraphSteps / per && le == hipSuccess; ++k)
+        le = batch_launch_steps(b, per);
     e = hipStreamEndCapture(b->stream, &g);
     if (le != hipSuccess) {
         if (e == hipSuccess) (void)hipGraphDestroy(g);
@@ -2075,10 +2220,17 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3])
         double best = 1e300;
         int best_bx = bx0, best_rows = rows0;
         for (int bx : kTuneWidths2)
-            for (int rows : kTuneRows2) {
+            for (int k = -1; k < (int)(sizeof(kTuneRows2) / sizeof(int)); ++k) {
+                // k = -1: the default segment length for this width
                 Tiles tl;
-                const int r = std::min(rows, h->p.ny);
-                if (!make_tiles2(h->p.nx, h->p.ny, bx, r, align, &tl)) continue;
+                int r = 0;
+                if (k < 0) {
+                    if (!default_rows2(h->p.nx, h->p.ny, h->p.storage, bx, h->cus, &r, &tl))
+                        continue;
+                } else {
+                    r = std::min(kTuneRows2[k], h->p.ny);
+                    if (!make_tiles2(h->p.nx, h->p.ny, bx, r, align, &tl)) continue;
+                }
                 h->bx2 = bx;
                 h->seg_rows2 = r;
                 h->tiles2 = tl;
@@ -2164,16 +2316,22 @@ lbm_status lbm_batch_create(int32_t capacity, void *d_workspace, size_t workspac
     b->capacity = capacity;
     b->stream = (hipStream_t)hip_stream;
     b->d_table = (BatchEntry *)d_workspace;
-    b->d_steps =
+    b->d_ctr =
         (long long *)((char *)d_workspace + round_up((size_t)capacity * sizeof(BatchEntry), kAlign));
     b->steps_since_upload = 0;
+    b->launches_since_upload = 0;
     b->table_valid = false;
     b->storage = -1;
     b->force_on = -1;
     b->coll = -1;
+    b->fuse_max = 2;
     b->bx = 256;
     b->rows = 5;
+    b->bx2 = 256;
+    b->rows2 = kBatchRows2;
+    b->auto_rows2 = true;
     b->total_tiles = 0;
+    b->total_tiles2 = 0;
     b->graph_valid = false;
     *out = b;
     return LBM_OK;
@@ -2225,8 +2383,9 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
         const lbm_status st = batch_upload(b);
         if (st != LBM_OK) return st;
     }
-    int64_t done = 0;
-    // the legacy null stream cannot be captured: there every step is launched
+    int64_t done = 0, launches = 0;
+    const int per = batch_fuse(b);
+    // the legacy null stream cannot be captured: there every launch is made
     // on its own
     const bool graphs = b->stream != nullptr;
     if (graphs && nsteps >= kGraphSteps && !b->graph_valid) {
@@ -2243,22 +2402,23 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
             return LBM_ERR_DEVICE;
         }
         done += kGraphSteps;
+        launches += kGraphSteps / per;
     }
-    for (; done < nsteps; ++done) {
-        hipError_t e = launch_batch(b);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->stream, b->d_steps);
-            e = hipGetLastError();
-        }
+    while (done < nsteps) {
+        const int k = nsteps - done >= per ? per : 1;
+        const hipError_t e = batch_launch_steps(b, k);
         if (e != hipSuccess) {
             b->last_error = std::string("launching a batched step: ") + hipGetErrorString(e);
             return LBM_ERR_DEVICE;
         }
+        done += k;
+        ++launches;
     }
     b->steps_since_upload += nsteps;
+    b->launches_since_upload += launches;
     for (lbm_handle *h : b->members) {
         h->t += nsteps;
-        if (nsteps & 1) std::swap(h->cur, h->nxt);
+        if (launches & 1) std::swap(h->cur, h->nxt);
     }
     return LBM_OK;
 }
@@ -2267,6 +2427,35 @@ lbm_status lbm_batch_autotune(lbm_batch *b, double out[3])
 {
     if (!b) return LBM_ERR_INVALID_ARG;
     if (b->members.empty()) return LBM_OK;
+    if (batch_fuse(b) == 2) {
+        double best = 1e300;
+        int best_bx = b->bx2, best_rows = b->rows2;
+        b->auto_rows2 = false;
+        for (int bx : kTuneWidths2)
+            for (int rows : kBatchRowsCand2) {
+                b->bx2 = bx;
+                b->rows2 = rows;
+                if (batch_upload(b) != LBM_OK) continue;
+                // the counters stay 0: every timed launch reads the same buffers
+                const double us = time_launches(b->stream, 3, [&] { return launch_batch2(b); });
+                if (us >= 0 && us < best) {
+                    best = us;
+                    best_bx = bx;
+                    best_rows = rows;
+                }
+            }
+        b->bx2 = best_bx;
+        b->rows2 = best_rows;
+        b->auto_rows2 = false;
+        const lbm_status st = batch_upload(b);
+        if (st != LBM_OK) return st;
+        if (out) {
+            out[0] = best_bx;
+            out[1] = best_rows;
+            out[2] = 0.5 * best;  // per time step
+        }
+        return LBM_OK;
+    }
     const int bx0 = b->bx, rows0 = b->rows;
     double best = 1e300;
     int best_bx = bx0, best_rows = rows0;
@@ -2294,6 +2483,22 @@ lbm_status lbm_batch_autotune(lbm_batch *b, double out[3])
     }
     return LBM_OK;
 }
+
+lbm_status lbm_batch_set_fusion(lbm_batch *b, int32_t steps)
+{
+    if (!b || (steps != 1 && steps != 2)) return LBM_ERR_INVALID_ARG;
+    if (steps != b->fuse_max) {
+        b->fuse_max = steps;
+        b->table_valid = false;  // the table holds the two-step tiles only when used
+        if (b->graph_valid) {
+            (void)hipGraphExecDestroy(b->graph);
+            b->graph_valid = false;
+        }
+    }
+    return LBM_OK;
+}
+
+int32_t lbm_batch_get_fusion(const lbm_batch *b) { return b ? batch_fuse(b) : -1; }
 
 void lbm_batch_destroy(lbm_batch *b)
 {

@@ -134,6 +134,10 @@ def _load():
         lib.lbm_batch_step.restype = ctypes.c_int
         lib.lbm_batch_autotune.argtypes = [B, D3]
         lib.lbm_batch_autotune.restype = ctypes.c_int
+        lib.lbm_batch_set_fusion.argtypes = [B, ctypes.c_int32]
+        lib.lbm_batch_set_fusion.restype = ctypes.c_int
+        lib.lbm_batch_get_fusion.argtypes = [B]
+        lib.lbm_batch_get_fusion.restype = ctypes.c_int32
         lib.lbm_batch_destroy.argtypes = [B]
         lib.lbm_batch_destroy.restype = None
         S = ctypes.c_void_p
@@ -163,7 +167,8 @@ EXPORTED = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_sync", "lbm_mome
             "lbm_diagnostics", "lbm_get_populations", "lbm_set_populations", "lbm_time",
             "lbm_set_launch", "lbm_set_fusion", "lbm_get_fusion", "lbm_get_launch", "lbm_autotune", "lbm_batch_workspace_bytes",
             "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
-            "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_destroy", "lbm_status_string",
+            "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_set_fusion",
+            "lbm_batch_get_fusion", "lbm_batch_destroy", "lbm_status_string",
             "lbm_last_error", "lbm_destroy", "lbm_server_create", "lbm_server_job_bytes",
             "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
             "lbm_server_get_stats", "lbm_server_destroy")
@@ -309,6 +314,14 @@ def lbm_batch_autotune(b):
     out = (ctypes.c_double * 3)()
     _check_b(_load().lbm_batch_autotune(b, out))
     return int(out[0]), int(out[1]), float(out[2])
+
+
+def lbm_batch_set_fusion(b, steps):
+    _check_b(_load().lbm_batch_set_fusion(b, int(steps)))
+
+
+def lbm_batch_get_fusion(b):
+    return _load().lbm_batch_get_fusion(b)
 
 
 def lbm_batch_destroy(b):
@@ -483,6 +496,12 @@ class Batch:
 
     def autotune(self):
         return lbm_batch_autotune(self.handle)
+
+    def set_fusion(self, steps):
+        lbm_batch_set_fusion(self.handle, steps)
+
+    def fusion(self):
+        return lbm_batch_get_fusion(self.handle)
 
     def close(self):
         if self.handle:

@@ -1,6 +1,6 @@
-"""Batched stepping (one kernel launch per step for many lattices, HIP graph
-replays) and the autotuner, through the C ABI.  A batched lattice must give
-exactly the bits it gives when stepped alone."""
+"""Batched stepping (one kernel launch per two steps, or per step, for many
+lattices, HIP graph replays) and the autotuner, through the C ABI.  A batched
+lattice must give exactly the bits it gives when stepped alone."""
 import numpy as np
 import pytest
 import torch
@@ -28,20 +28,24 @@ def _mixed(storage="f64", count=6, seed=3):
     return W.batch_case(count=count, seed=seed, storage=storage, side_range=(24, 160))
 
 
+@pytest.mark.parametrize("fusion", [2, 1])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "f16l"])
-def test_batch_equals_alone(storage):
-    # eager steps (3), then graph replays (8-step graphs) with checks and
-    # eager work in between, then a remainder: every lattice bitwise equal to
-    # its solo run after each stage.
+def test_batch_equals_alone(storage, fusion):
+    # eager launches (3 steps: one two-step launch and a single step), then
+    # graph replays (8-step graphs) with checks and eager work in between,
+    # one single step that flips the launch parity, then remainders: every
+    # lattice bitwise equal to its solo run after each stage.
     require_gpu()
     cases = _mixed(storage)
     solo = [gpu_lattice(p, r) for p, r in cases]
     mates = [gpu_lattice(p, r) for p, r in cases]
     batch = lbm.Batch(len(cases))
+    batch.set_fusion(fusion)
     for lat in mates:
         batch.add(lat)
+    assert batch.fusion() == (1 if storage == "f16l" else fusion)
     done = 0
-    for n in (3, 8, 8, 16, 5):
+    for n in (3, 8, 8, 1, 16, 5, 2):
         batch.step(n)
         for s in solo:
             s.step(n)
@@ -79,6 +83,30 @@ def test_membership_changes_and_outside_steps():
         assert torch.equal(solo[k].populations(), mates[k].populations()), k
     with pytest.raises(lbm.LbmError):
         batch.add(mates[1])  # already a member
+
+
+def test_batch_fusion_switch_midway_and_bad_argument():
+    require_gpu()
+    cases = _mixed("f32", count=3, seed=10)
+    solo = [gpu_lattice(p, r) for p, r in cases]
+    mates = [gpu_lattice(p, r) for p, r in cases]
+    batch = lbm.Batch(3)
+    for m in mates:
+        batch.add(m)
+    assert batch.fusion() == 2
+    batch.step(9)
+    batch.set_fusion(1)
+    batch.step(10)
+    batch.set_fusion(2)
+    batch.step(13)
+    for s in solo:
+        s.step(32)
+    for s, m in zip(solo, mates):
+        assert m.t == 32 and torch.equal(s.populations(), m.populations())
+    for bad in (0, 3, -1):
+        with pytest.raises(lbm.LbmError):
+            batch.set_fusion(bad)
+    assert batch.fusion() == 2
 
 
 def test_batch_rejects_mixed_storage_and_full():
