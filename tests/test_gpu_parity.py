@@ -104,18 +104,22 @@ def test_paper_eos_droplet(oracle):
 
 
 def test_full_size_slab_first_steps(oracle):
-    # 2048 x 2048 slab at T_r = 0.7 in the benchmark's default launch shape,
-    # compared element by element after 3 steps.
+    # 2048 x 2048 slab at T_r = 0.7 in the benchmark's launch configuration
+    # (the default: one two-step launch in the default shape), compared
+    # element by element at t = 2; then one single-step launch (an odd
+    # remainder), compared at t = 3.
     require_gpu()
-    log("case slab 2048x2048, 3 steps")
+    log("case slab 2048x2048, 2 + 1 steps")
     p, rho0 = W.slab_case(n=2048, tr=0.7)
     P = oracle_params(oracle, p)
     f = oracle.init(P, rho0)
     lat = gpu_lattice(p, rho0)
+    assert lat.fusion() == 2
     log(f"  launch {lat.launch()}")
-    lat.step(3)
-    oracle.step(P, f, 3)
-    assert_parity(gpu_state(lat), oracle_state(oracle, P, f), what="t=3")
+    for n, t in ((2, 2), (1, 3)):
+        lat.step(n)
+        oracle.step(P, f, n)
+        assert_parity(gpu_state(lat), oracle_state(oracle, P, f), what=f"t={t}")
 
 
 @pytest.mark.parametrize("tr", [0.6, 0.7, 0.8, 0.9])
