@@ -12,8 +12,8 @@ single-step launch per lattice.  Inputs are resident in HBM before timing.
 
 Output: one JSON line.  `value` is lattice updates per second over the timed
 steps (MLUPS).  `roofline` prices the dominant kernel (the two-step pass; the
-single-step sweep for the per-cell-reference FP16 mode, which has no two-step
-kernel) against the 8 TB/s HBM peak with its algorithmic bytes per launch: 144
+single-step sweep with --fusion 1) against the 8 TB/s HBM peak with its
+algorithmic bytes per launch: 144
 per cell for FP64 (9 populations read + 9 written once per launch, whether the
 launch advances one step or two), using the kernel's average duration timed
 with HIP events on the library's stream.  `cpu_baseline` times the CPU oracle
@@ -119,8 +119,9 @@ def cpu_baseline(budget_s=12.0):
 def run_batch(args):
     """256 independent droplet lattices (sides log-uniform in [64, 512], T_r
     U[0.55, 0.95], sigma U[1/8, 4], R0 U[0.15, 0.35] side, seed 6) stepped by
-    one batched launch per two steps (the two-step pass; per step with
-    --storage f16l) with FP32-shifted storage, shape chosen by the autotuner,
+    one batched launch per two steps (the two-step pass) or per step, as the
+    autotuner finds faster (--fusion 1: single steps only), with FP32-shifted
+    storage, shape chosen by the autotuner,
     8-step HIP graphs replayed.  Beside it, the same lattices in FP64 stepped
     each on its own (the plain path: one two-step launch per lattice per two
     steps)."""
@@ -139,8 +140,8 @@ def run_batch(args):
             batch.set_fusion(args.fusion)
         for lat in lats:
             batch.add(lat)
+        bx, rows, us = batch.autotune()  # shape, and one or two steps per launch
         fusion = batch.fusion()
-        bx, rows, us = batch.autotune()
         err(f"batch of {len(lats)} lattices, {cells} cells; autotuned block {bx}, "
             f"rows {rows}: {us:.1f} us/step")
         batch.step(args.warmup)
@@ -196,7 +197,7 @@ def run_batch(args):
         "config": {
             "workload": "batch of 256 D2Q9 droplet lattices, sides log-uniform [64, 512], "
                         "T_r U[0.55,0.95], sigma U[1/8,4], R0 U[0.15,0.35] side, seed 6; "
-                        "one batched launch per two steps (per step for f16l), 8-step HIP "
+                        f"one batched launch per {fusion} step(s), 8-step HIP "
                         "graphs, autotuned shape",
             "storage": storage, "lattices": len(lats), "cells": cells,
             "steps_per_launch": fusion, "bytes_per_cell_and_launch": bpc,

@@ -207,10 +207,8 @@ lbm_status lbm_set_launch(lbm_handle *h, int32_t block_x, int32_t seg_rows);
  * each workgroup owns block_x - 6 columns, rounded down to the strip
  * alignment) and seg_rows (>= 1) set the two-step launch shape; 0 keeps the
  * library's choice (256 threads; segments of 2..40 rows, as many as fill whole
- * rounds of the workgroups the device runs at once).  lbm_init selects 2 for
- * every storage mode but LBM_STORE_F16_LOCAL, which has no two-step kernel
- * (there steps = 2 is LBM_ERR_INVALID_ARG).  Batches have their own setting
- * (lbm_batch_set_fusion). */
+ * rounds of the workgroups the device runs at once).  lbm_init selects 2.
+ * Batches have their own setting (lbm_batch_set_fusion). */
 lbm_status lbm_set_fusion(lbm_handle *h, int32_t steps, int32_t block_x, int32_t seg_rows);
 
 /* Time steps per pass in use (1 or 2); -1 for a NULL handle. */
@@ -221,14 +219,15 @@ int32_t lbm_get_fusion(const lbm_handle *h);
  * workgroups per launch. */
 lbm_status lbm_get_launch(const lbm_handle *h, int32_t out[3]);
 
-/* Pick the launch shape of the step kernel in use by measurement: time a few
- * launches for each candidate shape (single steps: workgroup widths 64..512,
- * segments of 3..17 rows; two-step pass: widths 128, 256, 512, each with its
- * default segment length and segments of 12..48 rows) and keep the fastest.
- * The timed launches write only the spare population buffer and are not
- * counted as steps, so the state and t are unchanged.  Synchronous; out (may
- * be NULL) receives the chosen block_x, seg_rows and the measured
- * microseconds per time step. */
+/* Pick the step kernel's launch shape by measurement: time a few launches for
+ * each candidate shape (single steps: workgroup widths 64..512, segments of
+ * 3..17 rows; two-step pass, when lbm_get_fusion is 2: widths 128, 256, 512,
+ * each with its default segment length and segments of 12..48 rows) and keep
+ * the fastest per time step, switching to single steps if they win (results
+ * are bitwise the same; lbm_get_fusion tells which).  The timed launches
+ * write only the spare population buffer and are not counted as steps, so
+ * the state and t are unchanged.  Synchronous; out (may be NULL) receives the
+ * chosen block_x, seg_rows and the measured microseconds per time step. */
 lbm_status lbm_autotune(lbm_handle *h, double out[3]);
 
 /* ---- Batches: many lattices advanced together by one kernel launch ----
@@ -236,8 +235,8 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3]);
  * A batch holds up to `capacity` handles created by lbm_init on the same HIP
  * stream, all with the same storage mode, force_on and collision, any sizes
  * and any other parameters.  lbm_batch_step launches one kernel per two time
- * steps (the two-step pass; one per step for LBM_STORE_F16_LOCAL or after
- * lbm_batch_set_fusion(b, 1), and for an odd last step) covering every tile
+ * steps (the two-step pass; one per step after lbm_batch_set_fusion(b, 1),
+ * and for an odd last step) covering every tile
  * of every lattice (a workgroup finds its lattice in a device table), and
  * replays a captured HIP graph of eight steps for every full eight steps of a
  * call (not on the legacy null stream, which cannot be captured: there each
@@ -269,15 +268,16 @@ int32_t lbm_batch_size(const lbm_batch *b);
 /* Advance every lattice of the batch by nsteps (asynchronous). */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
-/* Choose the batch's workgroup width and segment length (of the two-step
- * pass when the batch uses it) by timing candidate shapes on the batch as it
- * is (state unchanged, as lbm_autotune).  Synchronous; out (may be NULL):
+/* Choose the batch's workgroup width and segment length by timing candidate
+ * shapes on the batch as it is (state unchanged, as lbm_autotune): single
+ * steps, and the two-step pass unless lbm_batch_set_fusion(b, 1) was called
+ * (segments of 2..40 rows); the faster per time step is kept
+ * (lbm_batch_get_fusion tells which).  Synchronous; out (may be NULL):
  * block_x, seg_rows, microseconds per time step. */
 lbm_status lbm_batch_autotune(lbm_batch *b, double out[3]);
 
-/* Time steps per batched launch: 2 (the default; batches of
- * LBM_STORE_F16_LOCAL lattices still take single steps) or 1.  Results are
- * bitwise the same either way.  The next lbm_batch_step rewrites the table.
+/* Time steps per batched launch: 2 (the default) or 1.  Results are bitwise
+ * the same either way.  The next lbm_batch_step rewrites the table.
  * Until lbm_batch_autotune is called, the two-step segment length is chosen
  * at each table upload to fill whole rounds of the workgroups the device runs
  * at once (2..40 rows over all members). */

@@ -872,12 +872,16 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(c
 // 3 (row r) three, 5 and 6 (row r - 1) four.  Populations 0, 2 and 4 come
 // from the own lane and stay in registers.  Register sets rotate with period 6
 // (the loop is unrolled six times).
-template <class R, int BX>
+template <class R, int BX, bool LOC>
 struct Pass2Lds {
     R psi_a[3][BX], psi_b[3][BX];  // psi of A's and B's rows
     R p78[2][2][BX];               // populations 7, 8 of A's rows
     R p13[3][2][BX];               // populations 1, 3
     R p56[4][2][BX];               // populations 5, 6
+    // per-cell mode: the reference R of A's input rows (exchanged for the
+    // neighbours' values) and the new R of A's output rows (B reads it for
+    // rows r - 1, r, r + 1, so four rows live at once)
+    float r_in[LOC ? 2 : 1][BX], r_out[LOC ? 4 : 1][BX];
 };
 
 template <int BX, int PF, int FORCE, int ST, int COLL>
@@ -885,11 +889,12 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
                                       typename Store<ST>::E *__restrict__ dst, const Coeffs &c,
                                       long long t, int ys, int n, int x, const Cols &cols,
                                       bool active, bool valid_b, bool interior,
-                                      Pass2Lds<typename Store<ST>::R, BX> &L,
+                                      Pass2Lds<typename Store<ST>::R, BX, Store<ST>::local> &L,
                                       unsigned long long &bad)
 {
     using E = typename Store<ST>::E;
     using R = typename Store<ST>::R;
+    constexpr bool LOC = Store<ST>::local;
     static_assert(PF == 1, "the period-6 rotation assumes one row of prefetch");
     constexpr int K = PF + 2;
     const Phys<R> P(c);
@@ -911,6 +916,19 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     R fa[K][kQ];
     R rho_a[2], rho_b[2];   // rho of the last two psi rows of each step
     R h0[3], h2[6], h4[2];  // populations 0, 2, 4 of A's last post-collision rows
+    // per-cell mode: R triples of A's input rows (slot = (row + 1) mod 3), R
+    // of A's rows before their collision, R of the next rows in flight
+    Tri<R> ta[3];
+    R ra[2];
+    RefPair<R> rl[2];
+    const bool first = tx == 0;
+    // R at x - 1, x, x + 1 from a lane's own and side values and an LDS row
+    auto tri_from = [&](const RefPair<R> &v, const float *buf) {
+        return first ? Tri<R>{v.side, v.own, (R)buf[1]} : Tri<R>{(R)buf[txm], v.own, v.side};
+    };
+    auto tri_lds = [&](const float *buf) {
+        return Tri<R>{(R)buf[txm], (R)buf[tx], (R)buf[txp]};
+    };
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
 #pragma unroll
@@ -922,10 +940,29 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     for (int k = 0; k < 6; ++k)
         h2[k] = R(0);
     h0[0] = h0[1] = h0[2] = h4[0] = h4[1] = R(0);
+    ra[0] = ra[1] = R(0);
     // prologue: A's populations of rows -3 .. -4 + PF
 #pragma unroll
     for (int p = 0; p < PF; ++p)
         load_pulled<ST>(src, c, lrow(-3 + p), cols, fa[(1 + p) % K]);
+    if constexpr (LOC) {
+        // R triples of rows -4, -3, -2 (slots 0, 1, 2); R of row -1 in flight
+        const RefPair<R> q4 = load_ref<R>(src, c, lrow(-4), cols, first);
+        const RefPair<R> q3 = load_ref<R>(src, c, lrow(-3), cols, first);
+        const RefPair<R> q2 = load_ref<R>(src, c, lrow(-2), cols, first);
+        rl[1] = load_ref<R>(src, c, lrow(-1), cols, first);
+        rl[0] = rl[1];
+        L.r_in[0][tx] = (float)q4.own;
+        __syncthreads();
+        ta[0] = tri_from(q4, L.r_in[0]);
+        L.r_in[1][tx] = (float)q3.own;
+        __syncthreads();
+        ta[1] = tri_from(q3, L.r_in[1]);
+        L.r_in[0][tx] = (float)q2.own;
+        __syncthreads();
+        ta[2] = tri_from(q2, L.r_in[0]);
+        __syncthreads();
+    }
 
     // gates: the first iterations skip the work on rows no output needs (A's
     // collision of rows -4, -3, B's psi of rows -5 .. -2, B's collision of
@@ -939,13 +976,24 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
             const int s = m - 3 + PF;
             load_pulled<ST>(src, c, lrow(s < n + 2 ? s : n + 2), cols, fa[a_fetch]);
         }
-        // step A: rho and psi of row m - 3 (always one of A's rows -3 .. n + 2)
+        // step A: rho and psi of row m - 3 (always one of A's rows -3 .. n + 2);
+        // per-cell mode: its deviations are rebuilt from R of rows m - 4 ..
+        // m - 2 first, and R of row m - 1 is exchanged through the same barrier
         {
+            R ref_lead = gref;
+            if constexpr (LOC) {
+                reconstruct<R>(fa[a_lead], ta[J % 3], ta[(J + 1) % 3], ta[(J + 2) % 3]);
+                ref_lead = ta[(J + 1) % 3].o;
+                ra[J % 2] = ref_lead;
+                L.r_in[J % 2][tx] = (float)rl[(J + 1) % 2].own;
+                rl[J % 2] = load_ref<R>(src, c, lrow(m), cols, first);
+            }
             R psi;
-            const bool ok = rho_psi<FORCE, R>(fa[a_lead], gref, P, rho_a[J % 2], psi);
+            const bool ok = rho_psi<FORCE, R>(fa[a_lead], ref_lead, P, rho_a[J % 2], psi);
             if (active) check(ok, t, m - 3);
             L.psi_a[J % 3][tx] = psi;
             __syncthreads();
+            if constexpr (LOC) ta[J % 3] = tri_from(rl[(J + 1) % 2], L.r_in[J % 2]);
         }
         // step A: collision of row m - 4; B's share of it to LDS and registers
         if constexpr (DO_A) {
@@ -960,14 +1008,31 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
             }
             R *g = fa[a_cur];
             const R rho = rho_a[(J + 1) % 2];
+            const R ref_cur = LOC ? ra[(J + 1) % 2] : gref;
             R ux, uy;
             velocity<R>(g, rho, Fx, Fy, ux, uy);
             if constexpr (COLL == LBM_COLL_MRT)
                 collide_mrt<R>(g, rho, ux, uy, Fx, Fy, P);
             else
-                collide<R>(g, gref, rho, ux, uy, Fx, Fy, P);
-            // rounded to the storage type, as a single step stores them
-            auto rd = [&](int i) { return (R)(E)g[i]; };
+                collide<R>(g, ref_cur, rho, ux, uy, Fx, Fy, P);
+            // encoded as a single step stores them: rounded to the storage
+            // type; per-cell mode: X_i = round(d*_i - w_i s) with s the sum of
+            // the d*_i, and the new R = ref + (s + rounding errors)
+            if constexpr (LOC) {
+                const R sd =
+                    (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) + g[8];
+                R err = R(0);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    const R w = i == 0 ? R(4.0 / 9.0) : (i < 5 ? R(1.0 / 9.0) : R(1.0 / 36.0));
+                    const R dev = fma(-w, sd, g[i]);
+                    const E X = (E)dev;
+                    err += dev - (R)X;
+                    g[i] = (R)X;
+                }
+                L.r_out[m & 3][tx] = (float)(ref_cur + (sd + err));
+            }
+            auto rd = [&](int i) { return LOC ? g[i] : (R)(E)g[i]; };
             h0[J % 3] = rd(0);
             h2[J] = rd(2);
             h4[J % 2] = rd(4);
@@ -1001,8 +1066,15 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
         if constexpr (DO_BPSI) {
             R g[kQ];
             pull_b(std::integral_constant<int, 0>{}, g);
+            R ref_b = gref;
+            if constexpr (LOC) {
+                // rows r + 1, r, r - 1 were handed over at m, m - 1, m - 2
+                const Tri<R> C = tri_lds(L.r_out[(m + 3) & 3]);
+                reconstruct<R>(g, tri_lds(L.r_out[(m + 2) & 3]), C, tri_lds(L.r_out[m & 3]));
+                ref_b = C.o;
+            }
             R psi;
-            const bool ok = rho_psi<FORCE, R>(g, gref, P, rho_b[J % 2], psi);
+            const bool ok = rho_psi<FORCE, R>(g, ref_b, P, rho_b[J % 2], psi);
             if (valid_b && m - 5 >= -1) check(ok, t + 1, m - 5);
             L.psi_b[J % 3][tx] = psi;
         }
@@ -1011,6 +1083,13 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
         if constexpr (DO_BCOL) {
             R g[kQ];
             pull_b(std::integral_constant<int, 1>{}, g);
+            R ref_cur = gref;
+            if constexpr (LOC) {
+                // rows r + 1, r, r - 1 were handed over at m - 1, m - 2, m - 3
+                const Tri<R> C = tri_lds(L.r_out[(m + 2) & 3]);
+                reconstruct<R>(g, tri_lds(L.r_out[(m + 1) & 3]), C, tri_lds(L.r_out[(m + 3) & 3]));
+                ref_cur = C.o;
+            }
             R Fx = R(0), Fy = R(0);
             if (FORCE) {
                 const Row<R> T = psi_row(L.psi_b, (J + 1) % 3);
@@ -1026,14 +1105,35 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
             if constexpr (COLL == LBM_COLL_MRT)
                 collide_mrt<R>(g, rho, ux, uy, Fx, Fy, P);
             else
-                collide<R>(g, gref, rho, ux, uy, Fx, Fy, P);
+                collide<R>(g, ref_cur, rho, ux, uy, Fx, Fy, P);
             const int sb = m - 6;
             if (interior && sb >= 0 && sb < n) {
-                const size_t prow = (size_t)lrow(sb) * c.pitch;
+                const int yb = lrow(sb);
+                const size_t prow = (size_t)yb * c.pitch;
+                if constexpr (LOC) {
+                    // as the single-step store of the per-cell mode
+                    const R sd =
+                        (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) +
+                        g[8];
+                    R err = R(0);
 #pragma unroll
-                for (int i = 0; i < kQ; ++i)
-                    __builtin_nontemporal_store(
-                        (E)g[i], (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                    for (int i = 0; i < kQ; ++i) {
+                        const R w = i == 0 ? R(4.0 / 9.0) : (i < 5 ? R(1.0 / 9.0) : R(1.0 / 36.0));
+                        const R dev = fma(-w, sd, g[i]);
+                        const E X = (E)dev;
+                        err += dev - (R)X;
+                        __builtin_nontemporal_store(
+                            X, (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                    }
+                    float *rrow = (float *)((char *)dst + c.r_off) + (size_t)yb * c.r_pitch;
+                    __builtin_nontemporal_store((float)(ref_cur + (sd + err)),
+                                                (float *)((char *)rrow + 2 * cols.o));
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kQ; ++i)
+                        __builtin_nontemporal_store(
+                            (E)g[i], (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                }
             }
         }
     };
@@ -1071,7 +1171,7 @@ __device__ __forceinline__ void sweep2_tile(const void *__restrict__ src_v,
 {
     using E = typename Store<ST>::E;
     using R = typename Store<ST>::R;
-    __shared__ Pass2Lds<R, BX> lds;
+    __shared__ Pass2Lds<R, BX, Store<ST>::local> lds;
     const int seg = tile / tl.nstrips;
     const int strip = tile - seg * tl.nstrips;
     const int xs = strip * tl.width;
@@ -1511,7 +1611,7 @@ constexpr int kFuseBx = 256;
 
 int slots_per_cu2(int storage, int bx)
 {
-    const int per256 = storage == LBM_STORE_F16_SHIFTED ? 4 : 2;
+    const int per256 = is_f16(storage) ? 4 : 2;
     return std::max(1, per256 * 256 / bx);
 }
 
@@ -1619,6 +1719,7 @@ hipError_t launch_sweep2_f(lbm_handle *h, const void *src, void *dst)
     case LBM_STORE_F64: return launch_sweep2_c<FORCE, LBM_STORE_F64>(h, src, dst);
     case LBM_STORE_F32_SHIFTED: return launch_sweep2_c<FORCE, LBM_STORE_F32_SHIFTED>(h, src, dst);
     case LBM_STORE_F16_SHIFTED: return launch_sweep2_c<FORCE, LBM_STORE_F16_SHIFTED>(h, src, dst);
+    case LBM_STORE_F16_LOCAL: return launch_sweep2_c<FORCE, LBM_STORE_F16_LOCAL>(h, src, dst);
     }
     return hipErrorInvalidValue;
 }
@@ -1815,6 +1916,7 @@ hipError_t launch_batch2_f(lbm_batch *b)
     case LBM_STORE_F64: return launch_batch2_c<FORCE, LBM_STORE_F64>(b);
     case LBM_STORE_F32_SHIFTED: return launch_batch2_c<FORCE, LBM_STORE_F32_SHIFTED>(b);
     case LBM_STORE_F16_SHIFTED: return launch_batch2_c<FORCE, LBM_STORE_F16_SHIFTED>(b);
+    case LBM_STORE_F16_LOCAL: return launch_batch2_c<FORCE, LBM_STORE_F16_LOCAL>(b);
     }
     return hipErrorInvalidValue;
 }
@@ -1825,12 +1927,9 @@ hipError_t launch_batch2(lbm_batch *b)
     return b->force_on ? launch_batch2_f<1>(b) : launch_batch2_f<0>(b);
 }
 
-// Steps per launch of a batch: two where its storage mode has the two-step
-// kernel and the caller has not asked for single steps.
-int batch_fuse(const lbm_batch *b)
-{
-    return b->fuse_max == 2 && b->storage != LBM_STORE_F16_LOCAL ? 2 : 1;
-}
+// Steps per launch of a batch: two unless the caller has asked for single
+// steps.
+int batch_fuse(const lbm_batch *b) { return b->fuse_max; }
 
 // One batched launch of `steps` (1 or 2) steps and its counter bump.
 hipError_t batch_launch_steps(lbm_batch *b, int steps)
@@ -2039,12 +2138,11 @@ lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspac
         delete h;
         return LBM_ERR_INVALID_ARG;
     }
-    // two steps per pass wherever the storage mode has the two-step kernel
+    // two steps per pass wherever a default shape fits
     h->cus = device_cus();
     h->bx2 = kFuseBx;
-    h->fuse = params->storage != LBM_STORE_F16_LOCAL &&
-                      default_rows2(params->nx, params->ny, params->storage, h->bx2, h->cus,
-                                    &h->seg_rows2, &h->tiles2)
+    h->fuse = default_rows2(params->nx, params->ny, params->storage, h->bx2, h->cus,
+                            &h->seg_rows2, &h->tiles2)
                   ? 2
                   : 1;
 
@@ -2175,10 +2273,6 @@ lbm_status lbm_set_fusion(lbm_handle *h, int32_t steps, int32_t block_x, int32_t
         h->last_error = "steps per pass must be 1 or 2";
         return LBM_ERR_INVALID_ARG;
     }
-    if (h->p.storage == LBM_STORE_F16_LOCAL) {
-        h->last_error = "the two-step pass does not support the per-cell reference storage";
-        return LBM_ERR_INVALID_ARG;
-    }
     const int bx = block_x != 0 ? block_x : kFuseBx;
     if ((bx != 128 && bx != 256 && bx != 512) || seg_rows < 0) {
         h->last_error = "block_x must be 128, 256 or 512 and seg_rows >= 1";
@@ -2214,11 +2308,46 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3])
 {
     if (!h) return LBM_ERR_INVALID_ARG;
     const int align = strip_align(h->p.storage);
+    // single steps, always timed; launches cur -> nxt without swapping, so the
+    // state is not advanced
+    double best1 = 1e300;
+    int bx1 = h->bx, rows1 = h->seg_rows;
+    {
+        const int bx0 = h->bx, rows0 = h->seg_rows;
+        const Tiles tl0 = h->tiles;
+        for (int bx : kTuneWidths)
+            for (int rows : kTuneRows) {
+                Tiles tl;
+                if (!make_tiles(h->p.nx, h->p.ny, bx, std::min(rows, h->p.ny), align, &tl))
+                    continue;
+                h->bx = bx;
+                h->seg_rows = std::min(rows, h->p.ny);
+                h->tiles = tl;
+                const double us = time_launches(h->stream, 3, [&] {
+                    return launch_sweep<kStep>(h, h->cur, h->nxt, Fields{});
+                });
+                if (us < 0) {
+                    h->bx = bx0;
+                    h->seg_rows = rows0;
+                    h->tiles = tl0;
+                    return dev_fail(h, hipGetLastError(), "timing a launch shape");
+                }
+                if (us < best1) {
+                    best1 = us;
+                    bx1 = bx;
+                    rows1 = h->seg_rows;
+                }
+            }
+        make_tiles(h->p.nx, h->p.ny, bx1, rows1, align, &h->tiles);
+        h->bx = bx1;
+        h->seg_rows = rows1;
+    }
+    // the two-step pass, when in use (per time step: half a launch)
+    double best2 = 1e300;
+    int bx2 = h->bx2, rows2 = h->seg_rows2;
     if (h->fuse == 2) {
-        const int bx0 = h->bx2, rows0 = h->seg_rows2;
         const Tiles tl0 = h->tiles2;
-        double best = 1e300;
-        int best_bx = bx0, best_rows = rows0;
+        const int bx0 = h->bx2, rows0 = h->seg_rows2;
         for (int bx : kTuneWidths2)
             for (int k = -1; k < (int)(sizeof(kTuneRows2) / sizeof(int)); ++k) {
                 // k = -1: the default segment length for this width
@@ -2234,7 +2363,6 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3])
                 h->bx2 = bx;
                 h->seg_rows2 = r;
                 h->tiles2 = tl;
-                // cur -> nxt without swapping: the state is not advanced
                 const double us = time_launches(
                     h->stream, 3, [&] { return launch_sweep2(h, h->cur, h->nxt); });
                 if (us < 0) {
@@ -2243,56 +2371,22 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3])
                     h->tiles2 = tl0;
                     return dev_fail(h, hipGetLastError(), "timing a launch shape");
                 }
-                if (us < best) {
-                    best = us;
-                    best_bx = bx;
-                    best_rows = r;
+                if (0.5 * us < best2) {
+                    best2 = 0.5 * us;
+                    bx2 = bx;
+                    rows2 = r;
                 }
             }
-        make_tiles2(h->p.nx, h->p.ny, best_bx, best_rows, align, &h->tiles2);
-        h->bx2 = best_bx;
-        h->seg_rows2 = best_rows;
-        if (out) {
-            out[0] = best_bx;
-            out[1] = best_rows;
-            out[2] = 0.5 * best;  // per time step
-        }
-        return LBM_OK;
+        make_tiles2(h->p.nx, h->p.ny, bx2, rows2, align, &h->tiles2);
+        h->bx2 = bx2;
+        h->seg_rows2 = rows2;
+        if (best1 < best2) h->fuse = 1;
     }
-    const int bx0 = h->bx, rows0 = h->seg_rows;
-    const Tiles tl0 = h->tiles;
-    double best = 1e300;
-    int best_bx = bx0, best_rows = rows0;
-    for (int bx : kTuneWidths)
-        for (int rows : kTuneRows) {
-            Tiles tl;
-            if (!make_tiles(h->p.nx, h->p.ny, bx, std::min(rows, h->p.ny), align, &tl)) continue;
-            h->bx = bx;
-            h->seg_rows = std::min(rows, h->p.ny);
-            h->tiles = tl;
-            // cur -> nxt without swapping: the state is not advanced
-            const double us = time_launches(h->stream, 3, [&] {
-                return launch_sweep<kStep>(h, h->cur, h->nxt, Fields{});
-            });
-            if (us < 0) {
-                h->bx = bx0;
-                h->seg_rows = rows0;
-                h->tiles = tl0;
-                return dev_fail(h, hipGetLastError(), "timing a launch shape");
-            }
-            if (us < best) {
-                best = us;
-                best_bx = bx;
-                best_rows = h->seg_rows;
-            }
-        }
-    make_tiles(h->p.nx, h->p.ny, best_bx, best_rows, align, &h->tiles);
-    h->bx = best_bx;
-    h->seg_rows = best_rows;
     if (out) {
-        out[0] = best_bx;
-        out[1] = best_rows;
-        out[2] = best;
+        const bool two = h->fuse == 2;
+        out[0] = two ? bx2 : bx1;
+        out[1] = two ? rows2 : rows1;
+        out[2] = two ? best2 : best1;  // per time step
     }
     return LBM_OK;
 }
@@ -2427,59 +2521,56 @@ lbm_status lbm_batch_autotune(lbm_batch *b, double out[3])
 {
     if (!b) return LBM_ERR_INVALID_ARG;
     if (b->members.empty()) return LBM_OK;
-    if (batch_fuse(b) == 2) {
-        double best = 1e300;
-        int best_bx = b->bx2, best_rows = b->rows2;
+    const bool try_two = b->fuse_max == 2;
+    // single steps, always timed (a batch of many small lattices can be
+    // faster one step per launch); the counters stay 0 while timing, so every
+    // timed launch reads the same buffers
+    b->fuse_max = 1;
+    double best1 = 1e300;
+    int bx1 = b->bx, rows1 = b->rows;
+    for (int bx : kTuneWidths)
+        for (int rows : kTuneRows) {
+            b->bx = bx;
+            b->rows = rows;
+            if (batch_upload(b) != LBM_OK) continue;
+            const double us = time_launches(b->stream, 3, [&] { return launch_batch(b); });
+            if (us >= 0 && us < best1) {
+                best1 = us;
+                bx1 = bx;
+                rows1 = rows;
+            }
+        }
+    b->bx = bx1;
+    b->rows = rows1;
+    double best2 = 1e300;
+    int bx2 = b->bx2, rows2 = b->rows2;
+    if (try_two) {
+        b->fuse_max = 2;
         b->auto_rows2 = false;
         for (int bx : kTuneWidths2)
             for (int rows : kBatchRowsCand2) {
                 b->bx2 = bx;
                 b->rows2 = rows;
                 if (batch_upload(b) != LBM_OK) continue;
-                // the counters stay 0: every timed launch reads the same buffers
-                const double us = time_launches(b->stream, 3, [&] { return launch_batch2(b); });
-                if (us >= 0 && us < best) {
-                    best = us;
-                    best_bx = bx;
-                    best_rows = rows;
+                const double us =
+                    0.5 * time_launches(b->stream, 3, [&] { return launch_batch2(b); });
+                if (us >= 0 && us < best2) {
+                    best2 = us;
+                    bx2 = bx;
+                    rows2 = rows;
                 }
             }
-        b->bx2 = best_bx;
-        b->rows2 = best_rows;
-        b->auto_rows2 = false;
-        const lbm_status st = batch_upload(b);
-        if (st != LBM_OK) return st;
-        if (out) {
-            out[0] = best_bx;
-            out[1] = best_rows;
-            out[2] = 0.5 * best;  // per time step
-        }
-        return LBM_OK;
+        b->bx2 = bx2;
+        b->rows2 = rows2;
     }
-    const int bx0 = b->bx, rows0 = b->rows;
-    double best = 1e300;
-    int best_bx = bx0, best_rows = rows0;
-    for (int bx : kTuneWidths)
-        for (int rows : kTuneRows) {
-            b->bx = bx;
-            b->rows = rows;
-            if (batch_upload(b) != LBM_OK) continue;
-            // the step counter stays 0: every timed launch reads the same buffers
-            const double us = time_launches(b->stream, 3, [&] { return launch_batch(b); });
-            if (us >= 0 && us < best) {
-                best = us;
-                best_bx = bx;
-                best_rows = rows;
-            }
-        }
-    b->bx = best_bx;
-    b->rows = best_rows;
+    const bool two = try_two && best2 <= best1;
+    b->fuse_max = two ? 2 : 1;
     const lbm_status st = batch_upload(b);
     if (st != LBM_OK) return st;
     if (out) {
-        out[0] = best_bx;
-        out[1] = best_rows;
-        out[2] = best;
+        out[0] = two ? bx2 : bx1;
+        out[1] = two ? rows2 : rows1;
+        out[2] = two ? best2 : best1;  // per time step
     }
     return LBM_OK;
 }

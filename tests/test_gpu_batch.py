@@ -43,7 +43,7 @@ def test_batch_equals_alone(storage, fusion):
     batch.set_fusion(fusion)
     for lat in mates:
         batch.add(lat)
-    assert batch.fusion() == (1 if storage == "f16l" else fusion)
+    assert batch.fusion() == fusion
     done = 0
     for n in (3, 8, 8, 1, 16, 5, 2):
         batch.step(n)

@@ -3,8 +3,9 @@ on chip, rounded to the storage type) through the C ABI.
 
 It computes each step with the same device routines as a single step, on a
 tile widened by three columns and three rows on each side, so its populations
-must equal those of single steps bit for bit, in every storage mode that has
-it, with either collision, in every launch shape, on ragged and tiny lattices,
+must equal those of single steps bit for bit, in every storage mode (the
+per-cell FP16 mode hands its new reference densities over too), with either
+collision, in every launch shape, on ragged and tiny lattices,
 from even or odd starting times, and the first domain error it reports must
 be the oracle's (same step, same cell) whichever step of a pair it falls in.
 Beside that, parity with the FP64 oracle directly (the tolerance of the other
@@ -34,7 +35,7 @@ def _smooth_case(nx, ny, storage="f64", collision="bgk", seed=12):
 
 
 @pytest.mark.parametrize("collision", ["bgk", "mrt"])
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "f16l"])
 def test_two_step_pass_bitwise_equals_single_steps(storage, collision):
     require_gpu()
     p, rho0 = _smooth_case(301, 203, storage, collision)
@@ -63,19 +64,21 @@ def test_pairs_from_an_odd_time():
     assert torch.equal(lat.populations(), ref.populations())
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16l"])
 @pytest.mark.parametrize("nx,ny", [(3, 3), (5, 4), (17, 9), (250, 7), (251, 31)])
-def test_tiny_and_ragged_lattices(nx, ny):
+def test_tiny_and_ragged_lattices(nx, ny, storage):
     # lattices narrower than the halo (columns and rows wrap several times
-    # within one tile) and widths at and past one strip of 256 threads
+    # within one tile) and widths at and past one strip of 256 threads; the
+    # per-cell mode also exchanges its reference densities between lanes
     require_gpu()
-    p, rho0 = _smooth_case(nx, ny, "f64", "bgk", seed=14)
+    p, rho0 = _smooth_case(nx, ny, storage, "bgk", seed=14)
     ref = gpu_lattice(p, rho0, launch=(64, 1))
     ref.step(10)
     for shape in ((128, 1), (256, 3), (256, ny)):
         lat = gpu_lattice(p, rho0, fusion=(2,) + shape)
         lat.step(10)
         lat.sync()
-        assert torch.equal(lat.populations(), ref.populations()), (nx, ny, shape)
+        assert torch.equal(lat.populations(), ref.populations()), (nx, ny, storage, shape)
 
 
 def test_fp64_two_step_pass_matches_oracle(oracle):
@@ -97,17 +100,11 @@ def test_defaults_and_rejected_arguments():
     # default shape on a small lattice: one strip, segments of the minimum
     # length, 2 rows (more workgroups beat the halo rows when the lattice
     # cannot fill the device)
-    for storage in ("f64", "f32", "f16"):
+    for storage in ("f64", "f32", "f16", "f16l"):
         p, rho0 = _smooth_case(64, 48, storage)
         lat = gpu_lattice(p, rho0)
         assert lat.fusion() == 2
         assert lat.launch() == (256, 2, 24), storage
-    p, rho0 = _smooth_case(64, 48, "f16l")
-    lat = gpu_lattice(p, rho0)
-    assert lat.fusion() == 1
-    with pytest.raises(lbm.LbmError) as e:
-        lat.set_fusion(2)
-    assert e.value.status == lbm.LBM_ERR_INVALID_ARG and lat.fusion() == 1
     p, rho0 = _smooth_case(64, 48)
     lat = gpu_lattice(p, rho0)
     for bad in ((3,), (0,), (2, 192), (2, 64), (2, 256, -1)):
