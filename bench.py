@@ -481,6 +481,7 @@ def main():
             "traffic": traffic,
             "kernel": f"{kname}, {args.storage} storage, {args.collision})",
             "kernel_avg_ms": round(launch_ms, 5),
+            "steps_per_launch": 2 if kernel == "pass2" else 1,
         },
     }
     if not args.no_cpu_baseline and args.storage == "f64":
