@@ -16,8 +16,9 @@ single-step sweep with --fusion 1) against the 8 TB/s HBM peak with its
 algorithmic bytes per launch: 144
 per cell for FP64 (9 populations read + 9 written once per launch, whether the
 launch advances one step or two), using the kernel's average duration timed
-with HIP events on the library's stream.  `cpu_baseline` times the CPU oracle
-on a bounded sample of the same workload.
+with HIP events on the library's stream; beside it, the bandwidth of a plain
+device copy measured in the same run and the kernel's fraction of it.
+`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
 
 --storage f32 / f16 runs the same workload with populations stored as FP32 /
 FP16 deviations from w_i rho_ref (FP32 arithmetic; 72 / 36 bytes per cell).
@@ -92,6 +93,27 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     err(f"copy calibration: 5 copies of {a.numel() * 8} bytes (read + write each)")
+
+
+def copy_bandwidth_gbs(reps=5):
+    """Bandwidth of a plain device copy (torch copy_ of 1 GiB of FP64: 1 GiB
+    read + 1 GiB written per copy), the best of `reps`, in GB/s."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return 2 * (1 << 30) / (best / 1e3) / 1e9
 
 
 def cpu_baseline(budget_s=12.0):
@@ -446,6 +468,7 @@ def main():
     bpc = BYTES_PER_CELL[args.storage]
     achieved = bpc * N * N / (launch_ms / 1e3) / 1e9
     traffic = measured_traffic(kernel, args.storage) if args.collision == "bgk" else None
+    copy_gbs = copy_bandwidth_gbs()
 
     out = {
         "metric": METRIC,
@@ -482,6 +505,8 @@ def main():
             "kernel": f"{kname}, {args.storage} storage, {args.collision})",
             "kernel_avg_ms": round(launch_ms, 5),
             "steps_per_launch": 2 if kernel == "pass2" else 1,
+            "copy_kernel_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
     }
     if not args.no_cpu_baseline and args.storage == "f64":
