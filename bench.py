@@ -440,10 +440,21 @@ def main():
     em = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     pairs, odd = divmod(args.steps, 2)
+    # events at about every tenth of the paired steps (no synchronisation in
+    # between): per-block rates for the spread over the timed region
+    blk = max(1, pairs // 10)
+    marks = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    advance(2 * pairs)
+    done_pairs = 0
+    while done_pairs < pairs:
+        n = min(blk, pairs - done_pairs)
+        advance(2 * n)
+        done_pairs += n
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(stream)
+        marks.append((n, ev))
     em.record(stream)
     advance(odd)
     e1.record(stream)
@@ -453,6 +464,12 @@ def main():
         lat.sync()   # raises on a sticky domain error
     gpu_ms = e0.elapsed_time(e1)
     pair_ms = e0.elapsed_time(em)
+    block_rates, prev = [], e0
+    for n, ev in marks:
+        ms = prev.elapsed_time(ev)
+        if ms > 0:
+            block_rates.append(N * N * len(lats) * 2 * n / (ms / 1e3) / 1e6)
+        prev = ev
     err(f"timed {args.steps} steps: {gpu_ms:.2f} ms on the stream, {wall * 1e3:.2f} ms wall")
 
     cells = N * N * len(lats)
@@ -509,6 +526,13 @@ def main():
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },
     }
+    if len(block_rates) >= 5:
+        import numpy as np
+        out["value_spread"] = {
+            "blocks": len(block_rates), "unit": "MLUPS",
+            "p10": round(float(np.percentile(block_rates, 10)), 1),
+            "p50": round(float(np.percentile(block_rates, 50)), 1),
+            "p90": round(float(np.percentile(block_rates, 90)), 1)}
     if not args.no_cpu_baseline and args.storage == "f64":
         err("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline()
