@@ -946,22 +946,21 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     for (int p = 0; p < PF; ++p)
         load_pulled<ST>(src, c, lrow(-3 + p), cols, fa[(1 + p) % K]);
     if constexpr (LOC) {
-        // R triples of rows -4, -3, -2 (slots 0, 1, 2); R of row -1 in flight
+        // R triples of rows -4, -3, -2 (slots 0, 1, 2), exchanged through
+        // three rows of r_out behind one barrier (r_out is first written two
+        // iterations later, after two more barriers); R of row -1 in flight
         const RefPair<R> q4 = load_ref<R>(src, c, lrow(-4), cols, first);
         const RefPair<R> q3 = load_ref<R>(src, c, lrow(-3), cols, first);
         const RefPair<R> q2 = load_ref<R>(src, c, lrow(-2), cols, first);
         rl[1] = load_ref<R>(src, c, lrow(-1), cols, first);
         rl[0] = rl[1];
-        L.r_in[0][tx] = (float)q4.own;
+        L.r_out[0][tx] = (float)q4.own;
+        L.r_out[1][tx] = (float)q3.own;
+        L.r_out[2][tx] = (float)q2.own;
         __syncthreads();
-        ta[0] = tri_from(q4, L.r_in[0]);
-        L.r_in[1][tx] = (float)q3.own;
-        __syncthreads();
-        ta[1] = tri_from(q3, L.r_in[1]);
-        L.r_in[0][tx] = (float)q2.own;
-        __syncthreads();
-        ta[2] = tri_from(q2, L.r_in[0]);
-        __syncthreads();
+        ta[0] = tri_from(q4, L.r_out[0]);
+        ta[1] = tri_from(q3, L.r_out[1]);
+        ta[2] = tri_from(q2, L.r_out[2]);
     }
 
     // gates: the first iterations skip the work on rows no output needs (A's
