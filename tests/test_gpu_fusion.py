@@ -157,3 +157,30 @@ def test_domain_error_same_step_and_cell(oracle, disk, lead):
     assert len(set(msgs)) == 1, msgs
     assert (f"step {ref.value.fault.step}," in msgs[0]
             and f"cell {ref.value.fault.cell} " in msgs[0])
+
+
+def test_random_sizes_and_shapes_bitwise():
+    # seeded draws of lattice sizes around strip and segment boundaries,
+    # launch shapes, storage modes and collisions: the two-step pass equals
+    # single steps bit for bit in every draw
+    require_gpu()
+    rng = np.random.default_rng(21)
+    storages = ["f64", "f32", "f16", "f16l"]
+    for k in range(12):
+        bx = int(rng.choice([128, 256, 512]))
+        width = (bx - 6) // 32 * 32
+        nx = int(max(3, width * int(rng.integers(1, 4)) + int(rng.integers(-3, 4))))
+        ny = int(rng.integers(3, 90))
+        rows = int(rng.integers(1, ny + 1))
+        storage = storages[k % 4]
+        collision = "mrt" if k % 3 == 0 else "bgk"
+        p, rho0 = _smooth_case(nx, ny, storage, collision, seed=100 + k)
+        steps = int(rng.integers(2, 9))
+        ref = gpu_lattice(p, rho0, launch=(64, 3))
+        ref.step(steps)
+        lat = gpu_lattice(p, rho0, fusion=(2, bx, rows))
+        lat.step(steps)
+        lat.sync()
+        case = (nx, ny, bx, rows, storage, collision, steps)
+        log(f"  case {case}")
+        assert torch.equal(lat.populations(), ref.populations()), case
