@@ -524,6 +524,10 @@ def main():
             "steps_per_launch": 2 if kernel == "pass2" else 1,
             "copy_kernel_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
+            # the update rate against the HBM roofline of one step per pass
+            # (bytes_per_cell_and_launch per update at peak bandwidth)
+            "updates_vs_one_step_roofline": round(
+                mlups / (HBM_PEAK_GBS * 1e3 / bpc), 4),
         },
     }
     if len(block_rates) >= 5:
