@@ -1,4 +1,4 @@
-"""Throughput of the fused FP64 D2Q9 pseudopotential step on one MI355X.
+"""Throughput of the fused D2Q9 pseudopotential lattice update on one MI355X.
 
 Workload: four 2048 x 2048 periodic lattices, each a flat liquid slab in the
 middle half of the domain (tanh interfaces of width 2, seeded U(+-1e-3) noise)
@@ -10,31 +10,44 @@ populations once, compute both steps, write once), so the steps are issued in
 pairs, one launch per lattice per pair; an odd step count ends with one
 single-step launch per lattice.  Inputs are resident in HBM before timing.
 
+Before the timed region at least WARMUP_FLOOR_STEPS untimed steps run (more
+if --warmup asks for more), and the timed steps are enqueued right behind
+them with no host synchronisation in between, so the GPU does not idle into
+the timed region; every step, warm-up included, is checked for a sticky
+domain error after the timed region.
+
 Output: one JSON line.  `value` is lattice updates per second over the timed
 steps (MLUPS).  `roofline` prices the dominant kernel (the two-step pass; the
-single-step sweep with --fusion 1) against the 8 TB/s HBM peak with its
-algorithmic bytes per launch: 144
-per cell for FP64 (9 populations read + 9 written once per launch, whether the
-launch advances one step or two), using the kernel's average duration timed
-with HIP events on the library's stream; beside it, the bandwidth of a plain
-device copy measured in the same run and the kernel's fraction of it.
-`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+single-step sweep with --fusion 1) at the algorithmic bytes of a cell update,
+one read and one write of its populations (144 B in FP64, 72 / 36 / 44 B in
+the reduced-precision modes), times the updates one launch makes (two per
+cell for the two-step pass), over its average launch duration timed with HIP
+events on the library's stream, against the 8 TB/s HBM peak.  Because a
+two-step launch reads and writes the populations once for two updates, that
+fraction can exceed 1; `roofline.per_launch_hbm` gives the launch's own
+bytes (one read and one write per cell) against the peak and against a plain
+device copy measured in the same run.  `traffic` is the counter-measured HBM
+bytes per launch while the kernel source is the one the counters were taken
+on.
 
---storage f32 / f16 runs the same workload with populations stored as FP32 /
-FP16 deviations from w_i rho_ref (FP32 arithmetic; 72 / 36 bytes per cell).
+With the default FP64 BGK workload the line also carries
+  `precision`: the same workload in the FP32-, FP16- and per-cell-FP16-shifted
+      storage modes (a few hundred timed steps each), rate and speedup;
+  `serving`: a reduced seeded serving stream (Poisson arrivals) through the
+      continuous-batching server in each reduced-precision mode, p50/p99
+      time-to-result against the same jobs run one after another on the plain
+      FP64 path;
+  `cpu_baseline`: the CPU oracle on a bounded sample of the same workload, at
+      one thread and at all host threads, median of three runs each.
 
---collision mrt runs it with the MRT collision (moment matrix of Appendix A,
-Lambda = diag(1, ..., 1, 1/tau, 1/tau) as in the paper's oscillation runs).
-
---workload batch measures the batched form instead: 256 uneven droplet
-lattices in FP32-shifted storage (or --storage f16), one launch per step,
-against the same lattices stepped one by one in FP64.
-
---workload serve runs a Poisson stream of jobs through the continuous-batching
-server (FP32- and FP16-shifted) and reports p50/p99 time-to-result beside the
-same jobs run one after another on the plain FP64 path.
+--storage f32 / f16 / f16l runs the slab workload in that storage mode alone;
+--collision mrt with the MRT collision (moment matrix of Appendix A, Lambda =
+diag(1, ..., 1, 1/tau, 1/tau) as in the paper's oscillation runs).
+--workload batch measures 256 uneven droplet lattices in one batch;
+--workload serve the full 64-job serving stream.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-extras] [--serve-jobs J]
                        [--storage f64|f32|f16|f16l] [--collision bgk|mrt]
                        [--fusion 1|2] [--workload slab|batch|serve] [--jobs J]
        python bench.py --copy-calibration   (plain copy kernel for PMC scaling)
@@ -50,16 +63,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# 9 reads + 9 writes per cell and launch (and, for f16l, the per-cell FP32
-# reference): per cell update for single steps, per two updates for the
-# two-step pass
-BYTES_PER_CELL = {"f64": 144, "f32": 72, "f16": 36, "f16l": 44}
+# Algorithmic bytes of one cell update: 9 populations read + 9 written (and,
+# for f16l, the per-cell FP32 reference read and written).
+BYTES_PER_UPDATE = {"f64": 144, "f32": 72, "f16": 36, "f16l": 44}
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 METRIC = "MLUPS/GPU and % HBM roofline (FP64 vs FP32/FP16-shifted); p50/p99 time-to-result"
 N = 2048
 TEMPS = (0.6, 0.7, 0.8, 0.9)
-KERNEL_SRC = os.path.join(ROOT, "paper_2003_07968_amd", "csrc", "lbm.hip")
+WARMUP_FLOOR_STEPS = 200      # untimed steps before any timed region
+PRECISION_STEPS = 400         # timed steps per reduced-precision mode
+KERNEL_SRC = os.path.join(ROOT, "paper_2003_07968_amd", "csrc", "lbm_kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{storage}_2048.json")
+DTYPE = {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
+         "f16": "f32 arithmetic, f16-shifted storage",
+         "f16l": "f32 arithmetic, f16 storage with per-cell f32 reference"}
+# What limits each dominant kernel, from the committed SQ counter profiles
+# (profiles/*_sq_counters.md): wave-cycles waiting to issue, at waits and
+# barriers, and issuing.
+LIMITER = {
+    ("pass2", "f64"): "latency: FP64 dependency chains at two waves per SIMD "
+                      "(profiles/sweep2_pass_f64_2048_sq_counters.md)",
+}
 
 
 def err(msg):
@@ -116,7 +140,22 @@ def copy_bandwidth_gbs(reps=5):
     return 2 * (1 << 30) / (best / 1e3) / 1e9
 
 
-def cpu_baseline(budget_s=12.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(runs=3, steps_one=2, steps_all=6):
+    """The CPU oracle on one 2048 x 2048 slab of the workload (T_r = 0.8): the
+    median of `runs` timings of `steps_one` steps at one thread and of
+    `steps_all` steps at all host threads (about 20 s of CPU work)."""
+    import statistics
     from oracle import lbmref
     from paper_2003_07968_amd import workloads as W
     p, rho0 = W.slab_case(n=N, tr=0.8)
@@ -124,18 +163,29 @@ def cpu_baseline(budget_s=12.0):
                            sigma=p["sigma"], eos=(p["eos_a"], p["eos_b"], p["eos_c"],
                                                   p["eos_k"]), T=p["T"])
     f = lbmref.init(P, rho0)
+    all_threads = lbmref.threads()
     lbmref.step(P, f, 1)  # warm the pages
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        lbmref.step(P, f, 1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or steps >= 200:
-            break
-    mlups = N * N * steps / el / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": lbmref.threads(),
-            "kind": "oracle",
-            "sample": f"one 2048x2048 slab (T_r=0.8), {steps} oracle steps, {el:.1f} s"}
+
+    def median_rate(threads, steps):
+        lbmref.set_threads(threads)
+        rates, secs = [], []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            lbmref.step(P, f, steps)
+            el = time.perf_counter() - t0
+            rates.append(N * N * steps / el / 1e6)
+            secs.append(el)
+        return statistics.median(rates), sum(secs)
+
+    one, s_one = median_rate(1, steps_one)
+    full, s_full = median_rate(all_threads, steps_all)
+    lbmref.set_threads(all_threads)
+    return {"value": round(full, 3), "unit": "MLUPS", "cores": all_threads, "kind": "oracle",
+            "sample": f"one 2048x2048 slab (T_r=0.8), median of {runs} runs of {steps_all} "
+                      f"oracle steps at {all_threads} threads ({s_full:.1f} s) and of "
+                      f"{steps_one} steps at 1 thread ({s_one:.1f} s)",
+            "single_thread": {"value": round(one, 3), "unit": "MLUPS", "cores": 1},
+            "cpu_model": cpu_model()}
 
 
 def run_batch(args):
@@ -203,7 +253,7 @@ def run_batch(args):
             lat.sync()
     mlups = cells * args.steps / (gpu_ms / 1e3) / 1e6
     plain_mlups = cells * seq_steps / (plain_ms / 1e3) / 1e6
-    bpc = BYTES_PER_CELL[storage]
+    bpc = BYTES_PER_UPDATE[storage]
     step_ms = gpu_ms / args.steps
     launches = args.steps // fusion + args.steps % fusion
     launch_ms = gpu_ms / launches
@@ -288,22 +338,23 @@ def serve_stream(jobs, arrivals, storage, arena_bytes, quantum):
     return ttr, max(done_at.values()), stats
 
 
-def run_serve(args):
-    """Continuous batching of a Poisson stream of jobs (sides log-uniform in
-    [64, 1024], steps U[2000, 50000], droplet or slab, seed 7) in FP32- and
-    FP16-shifted storage, against running the same jobs one after another with
-    the plain FP64 path (first come, first served)."""
+def serve_measure(count, modes=("f32", "f16", "f16l")):
+    """Continuous batching of a seeded Poisson stream of `count` jobs (sides
+    log-uniform in [64, 1024], steps U[2000, 50000], droplet or slab, seed 7)
+    in each reduced-precision storage mode, against the same jobs run one
+    after another on the plain FP64 path (first come, first served).  The
+    arrival rate is 0.8 x the capacity measured on the first 16 jobs at 2000
+    steps each, all submitted at once."""
     import numpy as np
     import torch
     from paper_2003_07968_amd import lbm
     from paper_2003_07968_amd import workloads as W
 
-    jobs = W.serve_case(count=args.jobs, seed=7, storage="f32")
+    jobs = W.serve_case(count=count, seed=7, storage="f32")
     work = np.array([p["nx"] * p["ny"] * n for p, _, n in jobs], dtype=np.float64)
     arena = 48 << 30
     quantum = 128
 
-    # capacity: the first 16 jobs, 2000 steps each, all submitted at once
     cal = [(p, r, 2000) for p, r, _ in jobs[:16]]
     _, span, st = serve_stream(cal, np.zeros(len(cal)), "f32", arena, quantum)
     capacity = st["cell_steps"] / span
@@ -313,7 +364,7 @@ def run_serve(args):
         f"-> arrival rate {rate:.2f} jobs/s")
 
     served = {}
-    for storage in ("f32", "f16", "f16l"):
+    for storage in modes:
         ttr, span, st = serve_stream(jobs, arrivals, storage, arena, quantum)
         served[storage] = dict(_percentiles(ttr), mlups=round(st["cell_steps"] / span / 1e6, 1),
                                makespan_s=round(span, 3), rounds=st["rounds"],
@@ -343,30 +394,150 @@ def run_serve(args):
     seq = dict(_percentiles(ttr_seq), mlups=round(work.sum() / service.sum() / 1e6, 1),
                makespan_s=round(finish, 3))
     err(f"sequential fp64: {seq}")
+    return {
+        "jobs": len(jobs), "cell_updates": float(work.sum()), "arrival_rate_per_s": round(rate, 3),
+        "capacity_mlups": round(capacity / 1e6, 1), "quantum_steps": quantum,
+        "arena_bytes": arena, "served": served, "sequential_fp64": seq,
+        "p50_speedup_vs_sequential_fp64": {m: round(seq["p50_s"] / v["p50_s"], 2)
+                                           for m, v in served.items()},
+        "p99_speedup_vs_sequential_fp64": {m: round(seq["p99_s"] / v["p99_s"], 2)
+                                           for m, v in served.items()},
+    }
 
+
+def run_serve(args):
+    """The full serving stream (--jobs, default 64) as its own line."""
+    res = serve_measure(args.jobs)
     out = {
-        "metric": METRIC, "value": served["f32"]["mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "metric": METRIC, "value": res["served"]["f32"]["mlups"], "unit": "MLUPS", "n_gpus": 1,
         "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 arithmetic, f32-shifted storage", "data": "synthetic",
         "config": {
-            "workload": f"serving stream of {len(jobs)} D2Q9 jobs, Poisson arrivals at "
-                        f"{rate:.2f}/s (0.8 x measured capacity), sides log-uniform "
-                        "[64, 1024], steps U[2000, 50000], droplet or slab, T_r U[0.55,0.95], "
-                        "sigma U[1/8,4], seed 7; continuous batching, HBM-footprint admission",
-            "jobs": len(jobs), "cell_updates": float(work.sum()), "arrival_rate_per_s": rate,
-            "capacity_mlups": round(capacity / 1e6, 1), "quantum_steps": quantum,
-            "arena_bytes": arena,
+            "workload": f"serving stream of {res['jobs']} D2Q9 jobs, Poisson arrivals at "
+                        f"{res['arrival_rate_per_s']:.2f}/s (0.8 x measured capacity), sides "
+                        "log-uniform [64, 1024], steps U[2000, 50000], droplet or slab, T_r "
+                        "U[0.55,0.95], sigma U[1/8,4], seed 7; continuous batching, "
+                        "HBM-footprint admission",
         },
-        "time_to_result": {"served_f32": served["f32"], "served_f16": served["f16"],
-                           "served_f16l": served["f16l"],
-                           "sequential_fp64": seq,
-                           "p99_speedup_f32_vs_sequential_fp64":
-                               round(seq["p99_s"] / served["f32"]["p99_s"], 2),
-                           "p50_speedup_f32_vs_sequential_fp64":
-                               round(seq["p50_s"] / served["f32"]["p50_s"], 2)},
+        "serving": res,
     }
     print(json.dumps(out), flush=True)
+
+
+def serving_summary(count):
+    """The serving part of the default line: a reduced stream of `count` jobs."""
+    res = serve_measure(count)
+    res["note"] = (f"reduced stream: the first {count} jobs of the 64-job recipe "
+                   "(bench.py --workload serve runs all 64)")
+    return res
+
+
+def run_slab(storage, collision, fusion, steps, warmup):
+    """The four-temperature 2048^2 slab workload in one storage mode: untimed
+    warm-up (at least WARMUP_FLOOR_STEPS steps), then `steps` timed steps
+    enqueued right behind it, bracketed by events on the library's stream
+    (torch's current stream), with events at about every tenth of the paired
+    steps for the spread.  Every lattice's sticky error word is checked after
+    the timed region (it covers the warm-up too)."""
+    import torch
+    from paper_2003_07968_amd import lbm
+    from paper_2003_07968_amd import workloads as W
+
+    lats = []
+    for tr in TEMPS:
+        p, rho0 = W.slab_case(n=N, tr=tr)
+        p["storage"] = W.STORAGE[storage]
+        p["rho_ref"] = W.shift_reference(rho0, storage)
+        p["collision"] = W.COLLISION[collision]
+        lats.append(lbm.Lattice(p, rho0))
+        if fusion is not None:
+            lats[-1].set_fusion(fusion)
+    launch = lats[0].launch()
+    fus = lats[0].fusion()
+    torch.cuda.synchronize()
+    err(f"{storage}: lattices ready, {fus} step(s) per launch, launch shape {launch}")
+
+    def advance(nsteps):
+        for _ in range(nsteps // 2):
+            for lat in lats:
+                lat.step(2)
+        for _ in range(nsteps % 2):
+            for lat in lats:
+                lat.step(1)
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    em = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    pairs, odd = divmod(steps, 2)
+    blk = max(1, pairs // 10)
+    marks = []
+    wsteps = max(warmup, WARMUP_FLOOR_STEPS)
+    wsteps += wsteps % 2          # whole pairs, so the timed region starts on a pair
+    t0 = time.perf_counter()
+    advance(wsteps)
+    e0.record(stream)
+    done_pairs = 0
+    while done_pairs < pairs:
+        n = min(blk, pairs - done_pairs)
+        advance(2 * n)
+        done_pairs += n
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(stream)
+        marks.append((n, ev))
+    em.record(stream)
+    advance(odd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for lat in lats:
+        lat.sync()   # raises on a sticky domain error (warm-up or timed steps)
+    gpu_ms = e0.elapsed_time(e1)
+    pair_ms = e0.elapsed_time(em)
+    block_rates, prev = [], e0
+    for n, ev in marks:
+        ms = prev.elapsed_time(ev)
+        if ms > 0:
+            block_rates.append(N * N * len(lats) * 2 * n / (ms / 1e3) / 1e6)
+        prev = ev
+    err(f"{storage}: {wsteps} warm-up steps, then {steps} timed steps: {gpu_ms:.2f} ms on the "
+        f"stream ({wall * 1e3:.1f} ms wall including the warm-up)")
+    if fus == 2 and pairs > 0:
+        kernel, launch_ms = "pass2", pair_ms / (pairs * len(lats))
+        kname = "sweep2_kernel (two steps per launch"
+        timed_launches = pairs * len(lats) + odd * len(lats)
+    else:
+        kernel, launch_ms = "step", gpu_ms / (steps * len(lats))
+        kname = "sweep_kernel (one step per launch"
+        timed_launches = steps * len(lats)
+    res = {"mlups": N * N * len(lats) * steps / (gpu_ms / 1e3) / 1e6, "gpu_ms": gpu_ms,
+           "launch_ms": launch_ms, "kernel": kernel, "kernel_name": kname, "fusion": fus,
+           "launch": launch, "lattices": len(lats), "timed_launches": timed_launches,
+           "warmup_steps": wsteps, "block_rates": block_rates if len(block_rates) >= 5 else []}
+    del lats
+    torch.cuda.synchronize()
+    return res
+
+
+def precision_rates(f64_mlups):
+    """The slab workload in each reduced-precision storage mode (BGK, default
+    launch), PRECISION_STEPS timed steps each: rate, the dominant kernel's
+    launch time and the roofline fraction of its own bytes per update."""
+    out = {"steps": PRECISION_STEPS}
+    for st in ("f32", "f16", "f16l"):
+        r = run_slab(st, "bgk", None, PRECISION_STEPS, 0)
+        upl = 2 if r["kernel"] == "pass2" else 1
+        bpu = BYTES_PER_UPDATE[st]
+        achieved = bpu * upl * N * N / (r["launch_ms"] / 1e3) / 1e9
+        out[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS",
+                   "speedup_vs_f64": round(r["mlups"] / f64_mlups, 3),
+                   "bytes_per_cell_update": bpu, "steps_per_launch": r["fusion"],
+                   "kernel_avg_ms": round(r["launch_ms"], 5),
+                   "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
+                   "per_launch_hbm_frac": round(achieved / upl / HBM_PEAK_GBS, 4),
+                   "limiter": LIMITER.get((r["kernel"], st))}
+    return out
 
 
 def main():
@@ -376,12 +547,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--storage", choices=sorted(BYTES_PER_CELL), default="f64")
+    ap.add_argument("--storage", choices=sorted(BYTES_PER_UPDATE), default="f64")
     ap.add_argument("--collision", choices=("bgk", "mrt"), default="bgk")
     ap.add_argument("--workload", choices=("slab", "batch", "serve"), default="slab")
     ap.add_argument("--fusion", type=int, choices=(1, 2), default=None,
                     help="time steps per launch (default: the library's choice)")
     ap.add_argument("--jobs", type=int, default=64, help="jobs in the serving stream")
+    ap.add_argument("--serve-jobs", type=int, default=24,
+                    help="jobs in the reduced serving stream of the default line")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision and serving parts of the default line")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -403,89 +578,21 @@ def main():
         run_serve(args)
         return
 
-    from paper_2003_07968_amd import lbm
-    from paper_2003_07968_amd import workloads as W
-
-    lats = []
-    for tr in TEMPS:
-        p, rho0 = W.slab_case(n=N, tr=tr)
-        p["storage"] = W.STORAGE[args.storage]
-        p["rho_ref"] = W.shift_reference(rho0, args.storage)
-        p["collision"] = W.COLLISION[args.collision]
-        lats.append(lbm.Lattice(p, rho0))
-        if args.fusion is not None:
-            lats[-1].set_fusion(args.fusion)
-    launch = lats[0].launch()
-    fusion = lats[0].fusion()
-    err(f"lattices ready, {fusion} step(s) per launch, launch shape {launch}")
-
-    def advance(nsteps):
-        for _ in range(nsteps // 2):
-            for lat in lats:
-                lat.step(2)
-        for _ in range(nsteps % 2):
-            for lat in lats:
-                lat.step(1)
-
-    advance(args.warmup)
-    torch.cuda.synchronize()
-    for lat in lats:
-        lat.sync()
-    err(f"warmup {args.warmup} steps done")
-
-    # the library's stream is torch's current stream: events on it bracket
-    # exactly the step kernels; em splits the paired steps from the odd one
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    em = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    pairs, odd = divmod(args.steps, 2)
-    # events at about every tenth of the paired steps (no synchronisation in
-    # between): per-block rates for the spread over the timed region
-    blk = max(1, pairs // 10)
-    marks = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    done_pairs = 0
-    while done_pairs < pairs:
-        n = min(blk, pairs - done_pairs)
-        advance(2 * n)
-        done_pairs += n
-        ev = torch.cuda.Event(enable_timing=True)
-        ev.record(stream)
-        marks.append((n, ev))
-    em.record(stream)
-    advance(odd)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for lat in lats:
-        lat.sync()   # raises on a sticky domain error
-    gpu_ms = e0.elapsed_time(e1)
-    pair_ms = e0.elapsed_time(em)
-    block_rates, prev = [], e0
-    for n, ev in marks:
-        ms = prev.elapsed_time(ev)
-        if ms > 0:
-            block_rates.append(N * N * len(lats) * 2 * n / (ms / 1e3) / 1e6)
-        prev = ev
-    err(f"timed {args.steps} steps: {gpu_ms:.2f} ms on the stream, {wall * 1e3:.2f} ms wall")
-
-    cells = N * N * len(lats)
-    seconds = gpu_ms / 1e3
-    mlups = cells * args.steps / seconds / 1e6
-    # dominant kernel: the two-step pass when the steps came in pairs
-    if fusion == 2 and pairs > 0:
-        kernel, launch_ms = "pass2", pair_ms / (pairs * len(lats))
-        kname = "sweep2_kernel (two steps per launch"
-    else:
-        kernel, launch_ms = "step", gpu_ms / (args.steps * len(lats))
-        kname = "sweep_kernel (one step per launch"
-    bpc = BYTES_PER_CELL[args.storage]
-    achieved = bpc * N * N / (launch_ms / 1e3) / 1e9
+    res = run_slab(args.storage, args.collision, args.fusion, args.steps, args.warmup)
+    n_lat = res["lattices"]
+    bpu = BYTES_PER_UPDATE[args.storage]
+    kernel = res["kernel"]
+    upl = 2 if kernel == "pass2" else 1
+    launch_s = res["launch_ms"] / 1e3
+    # the roofline of one cell update: one read and one write of its
+    # populations (bpu bytes) at peak bandwidth; a two-step launch makes two
+    # updates per cell with one read and one write, so its update rate can
+    # exceed that figure
+    achieved = bpu * upl * N * N / launch_s / 1e9
+    launch_gbs = bpu * N * N / launch_s / 1e9
     traffic = measured_traffic(kernel, args.storage) if args.collision == "bgk" else None
     copy_gbs = copy_bandwidth_gbs()
+    mlups = res["mlups"]
 
     out = {
         "metric": METRIC,
@@ -494,23 +601,23 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(gpu_ms / args.steps, 5),
+        "ms_per_step": round(res["gpu_ms"] / args.steps, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
-                  "f16": "f32 arithmetic, f16-shifted storage",
-                  "f16l": "f32 arithmetic, f16 storage with per-cell f32 reference"}[args.storage],
+        "dtype": DTYPE[args.storage],
         "data": "synthetic",
         "config": {
             "workload": "D2Q9 2048x2048 periodic flat slab, T_r in {0.6,0.7,0.8,0.9} "
                         "(four lattices), tau=1, Carnahan-Starling a=1 b=4 R=1, G=-1, "
                         "eps=1.73, sigma=1, W=2, seeded +-1e-3 noise",
             "storage": args.storage, "collision": args.collision,
-            "lattices": len(lats), "nx": N, "ny": N,
-            "steps_per_launch": fusion,
-            "bytes_per_cell_and_launch": bpc,
-            "launch_block_x_seg_rows_workgroups": list(launch),
+            "lattices": n_lat, "nx": N, "ny": N,
+            "steps_per_launch": res["fusion"],
+            "bytes_per_cell_update": bpu,
+            "launch_block_x_seg_rows_workgroups": list(res["launch"]),
+            "timed_launches": res["timed_launches"],
+            "untimed_warmup_steps": res["warmup_steps"],
         },
         "roofline": {
             "bound": "hbm",
@@ -519,24 +626,30 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"{kname}, {args.storage} storage, {args.collision})",
-            "kernel_avg_ms": round(launch_ms, 5),
-            "steps_per_launch": 2 if kernel == "pass2" else 1,
-            "copy_kernel_gbs": round(copy_gbs, 1),
-            "frac_of_copy": round(achieved / copy_gbs, 4),
-            # the update rate against the HBM roofline of one step per pass
-            # (bytes_per_cell_and_launch per update at peak bandwidth)
-            "updates_vs_one_step_roofline": round(
-                mlups / (HBM_PEAK_GBS * 1e3 / bpc), 4),
+            "kernel": f"{res['kernel_name']}, {args.storage} storage, {args.collision})",
+            "kernel_avg_ms": round(res["launch_ms"], 5),
+            "updates_per_launch_per_cell": upl,
+            "limiter": LIMITER.get((kernel, args.storage)),
+            "per_launch_hbm": {
+                "bytes": bpu * N * N,
+                "achieved": round(launch_gbs, 1),
+                "frac": round(launch_gbs / HBM_PEAK_GBS, 4),
+                "copy_kernel_gbs": round(copy_gbs, 1),
+                "frac_of_copy": round(launch_gbs / copy_gbs, 4),
+            },
         },
     }
-    if len(block_rates) >= 5:
+    if res["block_rates"]:
         import numpy as np
+        br = res["block_rates"]
         out["value_spread"] = {
-            "blocks": len(block_rates), "unit": "MLUPS",
-            "p10": round(float(np.percentile(block_rates, 10)), 1),
-            "p50": round(float(np.percentile(block_rates, 50)), 1),
-            "p90": round(float(np.percentile(block_rates, 90)), 1)}
+            "blocks": len(br), "unit": "MLUPS",
+            "p10": round(float(np.percentile(br, 10)), 1),
+            "p50": round(float(np.percentile(br, 50)), 1),
+            "p90": round(float(np.percentile(br, 90)), 1)}
+    if args.storage == "f64" and args.collision == "bgk" and not args.no_extras:
+        out["precision"] = precision_rates(mlups)
+        out["serving"] = serving_summary(args.serve_jobs)
     if not args.no_cpu_baseline and args.storage == "f64":
         err("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline()

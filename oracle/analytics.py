@@ -45,6 +45,11 @@ class CarnahanStarling:
     c: float
     k: float
 
+    @property
+    def rho_max(self):
+        """Upper end of the density domain (packing limit b rho < 1)."""
+        return 1.0 / self.b
+
     def P(self, rho, T):
         br = self.b * rho
         return self.k * (self.c * rho * T * (1 + br + br**2 - br**3) / (1 - br) ** 3
@@ -93,6 +98,12 @@ def critical_point(eos: CarnahanStarling):
 
 
 def spinodals(eos: CarnahanStarling, T):
+    """Densities where dP/drho = 0 on either side of the unstable branch.  An
+    equation of state other than Carnahan-Starling supplies its own (any
+    object with P, dP, rho_max and spinodals(T) can be passed to the
+    coexistence routines below)."""
+    if not isinstance(eos, CarnahanStarling):
+        return eos.spinodals(T)
     rho_c, T_c, _ = critical_point(eos)
     if T >= T_c:
         raise ValueError("no two-phase region above T_c")
@@ -110,7 +121,7 @@ def _coexistence(eos, T, area):
 
     def roots(p0):
         rg = optimize.brentq(lambda r: eos.P(r, T) - p0, 1e-300, s1, xtol=1e-300, rtol=1e-15)
-        rl = optimize.brentq(lambda r: eos.P(r, T) - p0, s2, (1 - 1e-12) / eos.b,
+        rl = optimize.brentq(lambda r: eos.P(r, T) - p0, s2, (1 - 1e-12) * eos.rho_max,
                              xtol=1e-300, rtol=1e-15)
         return rg, rl
 
@@ -247,8 +258,14 @@ def lamb_period(gamma, rho_l, R_max, R_min, n=2):
 
 def fit_epsilon(eos, T, lo=1.0, hi=2.5, G=-1.0):
     """eps whose planar coexistence (Eq. PGLDR) gives Maxwell's liquid density
-    (the consistency condition of Eq. CTC, imposed at one temperature).  The
-    bracket is scanned first, since Eq. PGLDR has no solution for some eps."""
+    (the consistency condition of Eq. CTC, imposed at one temperature).  Both
+    coexistence densities are roots of P = p0, so matching the liquid density
+    matches p0 and the gas density too.  The bracket is scanned first, since
+    Eq. PGLDR has no solution for some eps.  For an equation of state that
+    satisfies Eq. CTC exactly with some eps0 the result is eps0; for the
+    Carnahan-Starling sets it is 1.89-1.93 (paper's constants) and 1.64-1.76
+    (a = b = c = k = 1) over T_r = 0.6 .. 0.9.  The paper's 1.73 was found by
+    adjusting lattice runs, not from Eq. PGLDR."""
     _, rl_m, _ = maxwell(eos, T)
 
     def diff(e):

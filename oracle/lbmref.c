@@ -39,6 +39,15 @@ int lbmref_threads(void)
 #endif
 }
 
+void lbmref_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Rounding to the storage formats.  binary16 has 11 significant bits, normal
  * numbers from 2^-14 to 65504 and subnormals spaced 2^-24; values from 65520
  * up round to infinity.  The spacing of representable values around |x| is

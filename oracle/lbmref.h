@@ -107,6 +107,7 @@ int lbmref_moments(const lbmref_params *p, const double *f, double *rho,
 int lbmref_step(const lbmref_params *p, double *f, int64_t nsteps,
                 lbmref_fault *fault);                     /* Eq. TLBE, nsteps times    */
 int lbmref_threads(void);                                  /* OpenMP threads it will use */
+void lbmref_set_threads(int n);                            /* use n > 0 threads from now on */
 
 /* Round x to the nearest value of the storage format (ties to even):
  * 0 -> x unchanged, 1 -> IEEE binary32, 2 -> IEEE binary16 (with subnormals,

@@ -80,6 +80,8 @@ def _load():
         lib.lbmref_moments.argtypes = [P, _DP] + [_DP] * 6 + [ctypes.POINTER(Fault)]
         lib.lbmref_step.argtypes = [P, _DP, ctypes.c_int64, ctypes.POINTER(Fault)]
         lib.lbmref_threads.argtypes = []
+        lib.lbmref_set_threads.argtypes = [ctypes.c_int]
+        lib.lbmref_set_threads.restype = None
         lib.lbmref_quantize.argtypes = [ctypes.c_int32, ctypes.c_double]
         lib.lbmref_quantize.restype = ctypes.c_double
         _lib = lib
@@ -118,6 +120,12 @@ def quantize(storage, x):
 
 def threads() -> int:
     return _load().lbmref_threads()
+
+
+def set_threads(n: int) -> None:
+    """Use n > 0 OpenMP threads in the following calls (timing only: every
+    result is independent of the thread count)."""
+    _load().lbmref_set_threads(int(n))
 
 
 def eos_pressure(p: Params, rho: float) -> float:
