@@ -171,6 +171,29 @@ lbm_status lbm_moments(lbm_handle *h, double *d_rho, double *d_ux, double *d_uy,
  * order (deterministic for a given lattice size).  Synchronous. */
 lbm_status lbm_diagnostics(lbm_handle *h, double out[6]);
 
+/* For callers that cannot allocate device memory or that must not depend on
+ * the workspace's reduction scratch (code that runs where hipMalloc is not
+ * allowed, tight serving loops): lbm_diagnostics with its per-workgroup
+ * partial sums and reduced values in a statically allocated device array of
+ * the library instead.  Same results, bitwise, as lbm_diagnostics on the
+ * same state (same kernels, same reduction order), and the same update of
+ * the steady-state snapshot, which stays in the handle's workspace.
+ *   - Allocates nothing: no hipMalloc, hipFree or allocating library call.
+ *     The array holds the partials of at most 16384 workgroups of the
+ *     diagnostics sweep plus six values (about 786 kB per device, held until
+ *     the process ends).  The default shapes stay far below that; a lattice
+ *     whose sweep needs more workgroups (very short segments set with
+ *     lbm_set_launch) is rejected with LBM_ERR_INVALID_ARG, nothing is
+ *     launched, and lbm_last_error says why.
+ *   - Every call on one GPU uses that GPU's single array: calls that overlap
+ *     on one GPU (from several host threads, or on several streams before
+ *     the earlier call has returned) race and must be serialised by the
+ *     caller.  The call is synchronous, so calls from one thread never
+ *     overlap.
+ *   - The handle's device (current at lbm_init) is made current for the
+ *     call and the caller's current device restored afterwards. */
+lbm_status lbm_diagnostics_noalloc(lbm_handle *h, double out[6]);
+
 /* Copy f(t) out to d_f ([9][ny][nx] FP64, device).  Synchronous.  With shifted
  * storage the values are w_i rho_ref + d_i, exactly. */
 lbm_status lbm_get_populations(lbm_handle *h, double *d_f);

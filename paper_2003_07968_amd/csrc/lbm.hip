@@ -6,6 +6,8 @@
 // instantiated in lbm_inst.hip.
 #include "lbm_kernels.hpp"
 
+#include <mutex>
+
 using namespace lbmk;
 
 namespace {
@@ -76,9 +78,46 @@ struct lbm_handle {
     int cus;                 // compute units of the device (default shapes)
     int bx2, seg_rows2;      // launch shape of the two-step pass
     Tiles tiles2;
+    int device;              // HIP device current at lbm_init
     lbm_status sticky;
     std::string last_error;
 };
+
+// ---- Statically allocated scratch (lbm_diagnostics_noalloc) ----
+//
+// The per-tile partial sums and the reduced values of one diagnostics sweep,
+// in a device array of fixed size instead of the workspace: at most
+// kNoAllocTiles workgroups (tiles of the single-step sweep), then kDiag
+// reduced values.  Every GPU the library runs on holds its own copy until
+// the process ends.  Host code never uses the array's name as an address: it
+// takes the device address from hipGetSymbolAddress, once per device, with
+// that device current.
+constexpr int kNoAllocTiles = 16384;
+constexpr size_t kScratchDoubles = (size_t)kNoAllocTiles * kDiag + kDiag;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device (null: not yet)
+
+// The device address of this device's scratch array (device `dev` must be
+// current).
+hipError_t scratch_on_device(int dev, double **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
 
 struct lbm_batch {
     int capacity;
@@ -358,9 +397,11 @@ SweepArgs sweep_args(const lbm_handle *h, const void *src, void *dst, Fields fo,
 }
 
 template <int MODE>
-hipError_t run_sweep(lbm_handle *h, const void *src, void *dst, Fields fo)
+hipError_t run_sweep(lbm_handle *h, const void *src, void *dst, Fields fo,
+                     double *partials = nullptr)
 {
-    const SweepArgs a = sweep_args(h, src, dst, fo, false);
+    SweepArgs a = sweep_args(h, src, dst, fo, false);
+    if (partials) a.partials = partials;
     switch (h->c.storage) {
     case LBM_STORE_F64: return launch_sweep<LBM_STORE_F64>(MODE, a);
     case LBM_STORE_F32_SHIFTED: return launch_sweep<LBM_STORE_F32_SHIFTED>(MODE, a);
@@ -684,6 +725,7 @@ lbm_status lbm_init(const lbm_params *params, void *d_workspace, size_t workspac
     }
     // two steps per pass wherever a default shape fits
     h->cus = device_cus();
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
     h->bx2 = kFuseBx;
     h->fuse = default_rows2(params->nx, params->ny, params->storage, h->bx2, h->cus,
                             &h->seg_rows2, &h->tiles2)
@@ -762,6 +804,42 @@ lbm_status lbm_diagnostics(lbm_handle *h, double out[6])
                        h->stream);
     if (e != hipSuccess) return dev_fail(h, e, "copying diagnostics");
     return read_sticky(h);
+}
+
+lbm_status lbm_diagnostics_noalloc(lbm_handle *h, double out[6])
+{
+    if (!h || !out) return LBM_ERR_INVALID_ARG;
+    if (h->tiles.ntiles > kNoAllocTiles) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "lbm_diagnostics_noalloc: the diagnostics sweep has %d workgroups, more "
+                      "than the %d its static scratch holds (a longer seg_rows in "
+                      "lbm_set_launch, or lbm_diagnostics, avoids this)",
+                      h->tiles.ntiles, kNoAllocTiles);
+        h->last_error = buf;
+        return LBM_ERR_INVALID_ARG;
+    }
+    // the handle's device current for the set-up and the launches
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return dev_fail(h, e, "querying the current device");
+    if (prev != h->device && (e = hipSetDevice(h->device)) != hipSuccess)
+        return dev_fail(h, e, "selecting the handle's device");
+    double *s = nullptr;
+    e = scratch_on_device(h->device, &s);
+    if (e == hipSuccess) e = run_sweep<kDiagnostics>(h, h->cur, nullptr, Fields{}, s);
+    double *red = s + (size_t)kNoAllocTiles * kDiag;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, h->stream, s,
+                           h->tiles.ntiles, red);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, red, kDiag * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    lbm_status st = e == hipSuccess ? read_sticky(h)
+                                    : dev_fail(h, e, "diagnostics with the static scratch");
+    if (prev != h->device) (void)hipSetDevice(prev);
+    return st;
 }
 
 lbm_status lbm_get_populations(lbm_handle *h, double *d_f)

@@ -95,6 +95,8 @@ def _load():
         lib.lbm_moments.restype = ctypes.c_int
         lib.lbm_diagnostics.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
         lib.lbm_diagnostics.restype = ctypes.c_int
+        lib.lbm_diagnostics_noalloc.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
+        lib.lbm_diagnostics_noalloc.restype = ctypes.c_int
         lib.lbm_get_populations.argtypes = [H, _VP]
         lib.lbm_get_populations.restype = ctypes.c_int
         lib.lbm_set_populations.argtypes = [H, _VP, ctypes.c_int64]
@@ -164,7 +166,7 @@ def _load():
 
 
 EXPORTED = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_sync", "lbm_moments",
-            "lbm_diagnostics", "lbm_get_populations", "lbm_set_populations", "lbm_time",
+            "lbm_diagnostics", "lbm_diagnostics_noalloc", "lbm_get_populations", "lbm_set_populations", "lbm_time",
             "lbm_set_launch", "lbm_set_fusion", "lbm_get_fusion", "lbm_get_launch", "lbm_autotune", "lbm_batch_workspace_bytes",
             "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
             "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_set_fusion",
@@ -235,6 +237,12 @@ def lbm_moments(h, rho=None, ux=None, uy=None, Fx=None, Fy=None, psi=None):
 def lbm_diagnostics(h):
     out = (ctypes.c_double * 6)()
     _check(h, _load().lbm_diagnostics(h, out))
+    return list(out)
+
+
+def lbm_diagnostics_noalloc(h):
+    out = (ctypes.c_double * 6)()
+    _check(h, _load().lbm_diagnostics_noalloc(h, out))
     return list(out)
 
 
