@@ -8,7 +8,9 @@ import torch
 from paper_2003_07968_amd import lbm
 from paper_2003_07968_amd import workloads as W
 
-from .gpu_common import gpu_lattice, log, require_gpu
+from .gpu_common import (PARITY_TOL, assert_parity, gpu_lattice, gpu_state, log,
+                         oracle_state, require_gpu)
+from .helpers import oracle_params
 
 pytestmark = pytest.mark.gpu
 
@@ -197,3 +199,36 @@ def test_batch_on_null_stream_runs_eagerly():
             s.step(19)
         for s, m in zip(solo, mates):
             assert torch.equal(s.populations(), m.populations())
+
+
+@pytest.mark.parametrize("fusion", [2, 1])
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_graph_replays_match_oracle(oracle, collision, fusion):
+    # 40 batched FP64 steps: five replays of the captured 8-step graph, with
+    # every lattice compared element by element with the CPU oracle after the
+    # first replay and at the end (the graph path against the oracle, not
+    # only against eager launches).
+    require_gpu()
+    cases = W.batch_case(count=3, seed=21, storage="f64", side_range=(20, 72))
+    mates = []
+    for p, r in cases:
+        p = dict(p)
+        if collision == "mrt":
+            p.update(collision=W.COLLISION["mrt"], tau_e=0.9, tau_zeta=1.1, tau_q=1.2)
+        mates.append((p, r, gpu_lattice(p, r)))
+    batch = lbm.Batch(len(mates))
+    batch.set_fusion(fusion)
+    for _, _, lat in mates:
+        batch.add(lat)
+    fos = [(oracle_params(oracle, p), oracle.init(oracle_params(oracle, p), r))
+           for p, r, _ in mates]
+    done = 0
+    for n in (8, 32):
+        batch.step(n)
+        done += n
+        for (p, _, lat), (P, f) in zip(mates, fos):
+            oracle.step(P, f, n)
+            lat.sync()
+            assert lat.t == done
+            assert_parity(gpu_state(lat), oracle_state(oracle, P, f), PARITY_TOL,
+                          f"{p['nx']}x{p['ny']} {collision} fusion {fusion} t={done}")

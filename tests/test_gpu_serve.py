@@ -90,10 +90,13 @@ def test_results_same_alone_and_in_the_mix():
     assert s["completed"] == len(jobs) and s["arena_used"] == tables  # all jobs' memory back
 
 
-def test_fp64_jobs_match_oracle(oracle):
+@pytest.mark.parametrize("quantum", [7, 24])
+def test_fp64_jobs_match_oracle(oracle, quantum):
+    # quantum 7 advances each round by launches of its own; quantum 24 also
+    # replays the batches' captured 8-step graphs
     require_gpu()
     jobs = _jobs(3, seed=12, storages=("f64",), sides=(20, 48), steps=(20, 60))
-    srv = lbm.Server(arena_bytes=64 << 20, max_resident=4, quantum=7)
+    srv = lbm.Server(arena_bytes=64 << 20, max_resident=4, quantum=quantum)
     ids = {srv.submit(p, r, n, want_populations=True): k for k, (p, r, n) in enumerate(jobs)}
     results = {}
     _drain(srv, results)
