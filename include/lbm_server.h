@@ -6,7 +6,7 @@
  * scheduling round (lbm_server_advance) admits waiting jobs while their
  * device-memory footprint fits in the server's arena and a resident slot is
  * free, advances every resident lattice by the same number of steps with one
- * batched launch per step (lbm_batch_step; one batch per storage mode, force
+ * batched launch per two steps (lbm_batch_step; one batch per storage mode, force
  * switch and collision operator, each holding a table for max_resident
  * lattices in the arena), and retires the jobs that have reached their step count,
  * copying their results to host memory.  A job's result is bitwise the one it
@@ -78,10 +78,14 @@ lbm_status lbm_server_submit(lbm_server *s, const lbm_params *p, const double *h
 /* One scheduling round: admit (queue order; a job that does not fit may be
  * overtaken by later ones, at most max_bypass times), advance every resident
  * lattice by min(quantum, the fewest steps any resident job still needs),
- * retire finished jobs.  Synchronous at the end of the round (the results of
- * the retired jobs are in host memory on return).  *n_retired (may be NULL)
- * receives the number of jobs retired in this round.  Returns LBM_OK, or
- * LBM_ERR_DEVICE on a HIP error (the server is then unusable). */
+ * retire finished jobs.  The call returns once the round is enqueued on the
+ * server's stream; it waits for the stream only in rounds that retire jobs
+ * (their results are in host memory on return) and, then and every 16
+ * rounds, to check the resident jobs' sticky errors: a job whose lattice has
+ * left the EOS domain is retired at that point with LBM_ERR_DOMAIN, without
+ * running its remaining steps.  *n_retired (may be NULL) receives the number
+ * of jobs retired in this round.  Returns LBM_OK, or LBM_ERR_DEVICE on a HIP
+ * error (the server is then unusable). */
 lbm_status lbm_server_advance(lbm_server *s, int32_t *n_retired);
 
 /* Move up to max finished jobs out of the server: ids[k] and status[k]
@@ -92,8 +96,9 @@ int32_t lbm_server_poll(lbm_server *s, int64_t *ids, int32_t *status, int32_t ma
 /* Counters of the server so far. */
 lbm_status lbm_server_get_stats(const lbm_server *s, lbm_server_stats *out);
 
-/* Free the server's host state.  Resident jobs are dropped (their device
- * memory is the arena's, which stays the caller's). */
+/* Wait for the server's stream, then free the server's host state.  Resident
+ * jobs are dropped (their device memory is the arena's, which stays the
+ * caller's and may be freed once this returns). */
 void lbm_server_destroy(lbm_server *s);
 
 #ifdef __cplusplus

@@ -12,16 +12,17 @@ using namespace lbmk;
 
 namespace {
 
-// Batch counters: p[0] steps, p[1] launches since the table was written.
-__global__ void bump_counter(long long *p, long long steps)
+// Batch counters of graph replays (batch_pos in lbm_kernels.hpp): p[0] steps
+// and p[1] launches since the table was written.
+__global__ void set_counters(long long *p, long long steps, long long launches)
+{
+    p[0] = steps;
+    p[1] = launches;
+}
+__global__ void bump_counters(long long *p, long long steps, long long launches)
 {
     p[0] += steps;
-    p[1] += 1;
-}
-__global__ void clear_counters(long long *p)
-{
-    p[0] = 0;
-    p[1] = 0;
+    p[1] += launches;
 }
 
 // Second stage of the diagnostics: one workgroup sums the per-tile partials
@@ -129,6 +130,8 @@ struct lbm_batch {
     std::vector<int64_t> t_at_upload;
     std::vector<void *> cur_at_upload, nxt_at_upload;
     long long steps_since_upload, launches_since_upload;
+    long long ctr_steps, ctr_launches;  // what the device counters hold once the
+                                        // work enqueued so far has run
     bool table_valid;
     int storage, force_on, coll;
     int fuse_max;             // steps per launch requested (1 or 2)
@@ -253,6 +256,14 @@ Coeffs make_coeffs(const lbm_params *p, const Layout &L)
 // Strip width alignment in columns: 128 bytes of FP64, 64 bytes of FP32 or FP16.
 int strip_align(int storage) { return is_f16(storage) ? 32 : 16; }
 
+// Strip width alignment of the two-step pass: 16 columns in every mode (128
+// bytes of FP64, 64 of FP32, 32 of FP16).  The FP16 passes are bound by
+// instruction issue, so the lanes a coarser alignment leaves idle cost more
+// than stores that share a cache line with the neighbouring strip's: on
+// 2048-wide lattices 256-lane workgroups make 9 strips of 240 columns instead
+// of 10 of 224.
+int strip_align2(int) { return 16; }
+
 bool make_tiles(int nx, int ny, int bx, int seg_rows, int align, Tiles *tl,
                 long long limit = kMaxTiles)
 {
@@ -339,6 +350,9 @@ void default_launch(int nx, int ny, int storage, int *bx_out, int *rows_out)
 // single steps; 8192^2 32..64 rows within 1%.
 constexpr int kFuseBx = 256;
 
+// Workgroups of the two-step pass one CU runs at once, per 256 threads: FP64
+// two (its waves per SIMD), FP32 two (as measured best, though four would
+// fit), FP16 four.
 int slots_per_cu2(int storage, int bx)
 {
     const int per256 = is_f16(storage) ? 4 : 2;
@@ -351,7 +365,7 @@ bool default_rows2(int nx, int ny, int storage, int bx, int cus, int *rows, Tile
 {
     const int min_rows = 2, max_rows = 40;
     Tiles t0;
-    if (!make_tiles2(nx, ny, bx, ny, strip_align(storage), &t0)) return false;
+    if (!make_tiles2(nx, ny, bx, ny, strip_align2(storage), &t0)) return false;
     const long long slots = (long long)slots_per_cu2(storage, bx) * cus;
     const long long per_round = std::max(1ll, slots / t0.nstrips);  // segments per round
     long long nseg = per_round;
@@ -360,7 +374,7 @@ bool default_rows2(int nx, int ny, int storage, int bx, int cus, int *rows, Tile
     if ((ny + nseg - 1) / nseg < min_rows) nseg = (ny + min_rows - 1) / min_rows;
     nseg = std::max(1ll, std::min<long long>(nseg, ny));
     for (int r = (int)((ny + nseg - 1) / nseg);; r = std::min(2 * r, ny)) {
-        if (make_tiles2(nx, ny, bx, r, strip_align(storage), tl)) {
+        if (make_tiles2(nx, ny, bx, r, strip_align2(storage), tl)) {
             *rows = r;
             return true;
         }
@@ -474,11 +488,14 @@ lbm_status read_sticky(lbm_handle *h)
 }
 
 
-BatchArgs batch_args(const lbm_batch *b, bool two)
+BatchArgs batch_args(const lbm_batch *b, bool two, const long long *ctr, long long steps_add,
+                     int launches_add)
 {
     return BatchArgs{b->d_table,
                      (int)b->members.size(),
-                     b->d_ctr,
+                     ctr,
+                     steps_add,
+                     launches_add,
                      two ? b->bx2 : b->bx,
                      (unsigned)(two ? b->total_tiles2 : b->total_tiles),
                      b->force_on,
@@ -486,10 +503,22 @@ BatchArgs batch_args(const lbm_batch *b, bool two)
                      b->stream};
 }
 
-// One batched step (the kernel only; the caller bumps the counters).
-hipError_t run_batch(lbm_batch *b)
+// One batched launch of `steps` (1 or 2) steps starting where batch_pos says:
+// eager launches pass the position (ctr = nullptr), captured ones their offset
+// from the device counters.
+hipError_t batch_launch_steps(lbm_batch *b, int steps, const long long *ctr, long long steps_add,
+                              int launches_add)
 {
-    const BatchArgs a = batch_args(b, false);
+    const BatchArgs a = batch_args(b, steps == 2, ctr, steps_add, launches_add);
+    if (steps == 2) {
+        switch (b->storage) {
+        case LBM_STORE_F64: return launch_batch2<LBM_STORE_F64>(a);
+        case LBM_STORE_F32_SHIFTED: return launch_batch2<LBM_STORE_F32_SHIFTED>(a);
+        case LBM_STORE_F16_SHIFTED: return launch_batch2<LBM_STORE_F16_SHIFTED>(a);
+        case LBM_STORE_F16_LOCAL: return launch_batch2<LBM_STORE_F16_LOCAL>(a);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (b->storage) {
     case LBM_STORE_F64: return launch_batch<LBM_STORE_F64>(a);
     case LBM_STORE_F32_SHIFTED: return launch_batch<LBM_STORE_F32_SHIFTED>(a);
@@ -499,34 +528,9 @@ hipError_t run_batch(lbm_batch *b)
     return hipErrorInvalidValue;
 }
 
-// One batched two-step launch (the kernel only).
-hipError_t run_batch2(lbm_batch *b)
-{
-    const BatchArgs a = batch_args(b, true);
-    switch (b->storage) {
-    case LBM_STORE_F64: return launch_batch2<LBM_STORE_F64>(a);
-    case LBM_STORE_F32_SHIFTED: return launch_batch2<LBM_STORE_F32_SHIFTED>(a);
-    case LBM_STORE_F16_SHIFTED: return launch_batch2<LBM_STORE_F16_SHIFTED>(a);
-    case LBM_STORE_F16_LOCAL: return launch_batch2<LBM_STORE_F16_LOCAL>(a);
-    }
-    return hipErrorInvalidValue;
-}
-
 // Steps per launch of a batch: two unless the caller has asked for single
 // steps.
 int batch_fuse(const lbm_batch *b) { return b->fuse_max; }
-
-// One batched launch of `steps` (1 or 2) steps and its counter bump.
-hipError_t batch_launch_steps(lbm_batch *b, int steps)
-{
-    hipError_t e = steps == 2 ? run_batch2(b) : run_batch(b);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->stream, b->d_ctr,
-                           (long long)steps);
-        e = hipGetLastError();
-    }
-    return e;
-}
 
 // Average duration in microseconds of `reps` calls of fn on `stream`, after
 // one untimed call.  Returns a negative value on a HIP error.
@@ -568,7 +572,7 @@ lbm_status batch_upload(lbm_batch *b)
     b->cur_at_upload.clear();
     b->nxt_at_upload.clear();
     int tile0 = 0, tile0_2 = 0;
-    const int align = strip_align(b->storage);
+    const int align = strip_align(b->storage), align2 = strip_align2(b->storage);
     const bool two = batch_fuse(b) == 2;
     if (two && b->auto_rows2 && !b->members.empty()) {
         // the segment length that minimises rounds x (rows + 6) over the whole
@@ -581,7 +585,7 @@ lbm_status batch_upload(lbm_batch *b)
             bool ok = true;
             for (const lbm_handle *h : b->members) {
                 Tiles t;
-                if (!make_tiles2(h->p.nx, h->p.ny, b->bx2, std::min(r, h->p.ny), align, &t)) {
+                if (!make_tiles2(h->p.nx, h->p.ny, b->bx2, std::min(r, h->p.ny), align2, &t)) {
                     ok = false;
                     break;
                 }
@@ -600,7 +604,7 @@ lbm_status batch_upload(lbm_batch *b)
         e.c = h->c;
         if (!make_tiles(h->p.nx, h->p.ny, b->bx, std::min(b->rows, h->p.ny), align, &e.tl,
                         1ll << 30) ||
-            (two && !make_tiles2(h->p.nx, h->p.ny, b->bx2, std::min(b->rows2, h->p.ny), align,
+            (two && !make_tiles2(h->p.nx, h->p.ny, b->bx2, std::min(b->rows2, h->p.ny), align2,
                                  &e.tl2))) {
             b->last_error = "launch shape does not fit a lattice of the batch";
             return LBM_ERR_INVALID_ARG;
@@ -626,7 +630,7 @@ lbm_status batch_upload(lbm_batch *b)
         e = hipMemcpyAsync(b->d_table, b->h_table.data(), b->h_table.size() * sizeof(BatchEntry),
                            hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(clear_counters, dim3(1), dim3(1), 0, b->stream, b->d_ctr);
+        hipLaunchKernelGGL(set_counters, dim3(1), dim3(1), 0, b->stream, b->d_ctr, 0ll, 0ll);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -640,6 +644,8 @@ lbm_status batch_upload(lbm_batch *b)
     }
     b->steps_since_upload = 0;
     b->launches_since_upload = 0;
+    b->ctr_steps = 0;
+    b->ctr_launches = 0;
     b->table_valid = true;
     return LBM_OK;
 }
@@ -659,18 +665,24 @@ bool batch_stale(const lbm_batch *b)
     return false;
 }
 
-// Capture kGraphSteps batched steps (launches of batch_fuse(b) steps, each
-// with its counter bump) in a graph.  An even number of launches, so a replay
-// leaves every lattice's state in the buffer it started from.
+// Capture kGraphSteps batched steps in a graph: launches of batch_fuse(b)
+// steps at their offsets from the device counters, then one kernel that
+// moves the counters on by the whole graph.  An even number of launches, so
+// a replay leaves every lattice's state in the buffer it started from.
 hipError_t batch_capture(lbm_batch *b)
 {
     hipGraph_t g;
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
-    const int per = batch_fuse(b);
-    for (int k = 0; k < kGraphSteps / per && le == hipSuccess; ++k)
-        le = batch_launch_steps(b, per);
+    const int per = batch_fuse(b), n = kGraphSteps / per;
+    for (int k = 0; k < n && le == hipSuccess; ++k)
+        le = batch_launch_steps(b, per, b->d_ctr, (long long)k * per, k);
+    if (le == hipSuccess) {
+        hipLaunchKernelGGL(bump_counters, dim3(1), dim3(1), 0, b->stream, b->d_ctr,
+                           (long long)kGraphSteps, (long long)n);
+        le = hipGetLastError();
+    }
     e = hipStreamEndCapture(b->stream, &g);
     if (le != hipSuccess) {
         if (e == hipSuccess) (void)hipGraphDestroy(g);
@@ -905,7 +917,7 @@ lbm_status lbm_set_fusion(lbm_handle *h, int32_t steps, int32_t block_x, int32_t
     int rows = seg_rows;
     Tiles tl;
     if (rows == 0 ? !default_rows2(h->p.nx, h->p.ny, h->p.storage, bx, h->cus, &rows, &tl)
-                  : !make_tiles2(h->p.nx, h->p.ny, bx, rows, strip_align(h->p.storage), &tl)) {
+                  : !make_tiles2(h->p.nx, h->p.ny, bx, rows, strip_align2(h->p.storage), &tl)) {
         h->last_error = "launch shape needs too many workgroups";
         return LBM_ERR_INVALID_ARG;
     }
@@ -982,7 +994,8 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3])
                         continue;
                 } else {
                     r = std::min(kTuneRows2[k], h->p.ny);
-                    if (!make_tiles2(h->p.nx, h->p.ny, bx, r, align, &tl)) continue;
+                    if (!make_tiles2(h->p.nx, h->p.ny, bx, r, strip_align2(h->p.storage), &tl))
+                        continue;
                 }
                 h->bx2 = bx;
                 h->seg_rows2 = r;
@@ -1001,7 +1014,7 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3])
                     rows2 = r;
                 }
             }
-        make_tiles2(h->p.nx, h->p.ny, bx2, rows2, align, &h->tiles2);
+        make_tiles2(h->p.nx, h->p.ny, bx2, rows2, strip_align2(h->p.storage), &h->tiles2);
         h->bx2 = bx2;
         h->seg_rows2 = rows2;
         if (best1 < best2) h->fuse = 1;
@@ -1038,6 +1051,8 @@ lbm_status lbm_batch_create(int32_t capacity, void *d_workspace, size_t workspac
         (long long *)((char *)d_workspace + round_up((size_t)capacity * sizeof(BatchEntry), kAlign));
     b->steps_since_upload = 0;
     b->launches_since_upload = 0;
+    b->ctr_steps = 0;
+    b->ctr_launches = 0;
     b->table_valid = false;
     b->storage = -1;
     b->force_on = -1;
@@ -1114,17 +1129,29 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
         }
     }
     while (graphs && nsteps - done >= kGraphSteps) {
-        const hipError_t e = hipGraphLaunch(b->graph, b->stream);
+        // the replay starts from the device counters: set them where the
+        // batch is if eager launches have moved it on since
+        const long long s0 = b->steps_since_upload + done, l0 = b->launches_since_upload + launches;
+        hipError_t e = hipSuccess;
+        if (b->ctr_steps != s0 || b->ctr_launches != l0) {
+            hipLaunchKernelGGL(set_counters, dim3(1), dim3(1), 0, b->stream, b->d_ctr, s0, l0);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipGraphLaunch(b->graph, b->stream);
         if (e != hipSuccess) {
             b->last_error = std::string("launching the batch graph: ") + hipGetErrorString(e);
             return LBM_ERR_DEVICE;
         }
         done += kGraphSteps;
         launches += kGraphSteps / per;
+        b->ctr_steps = s0 + kGraphSteps;
+        b->ctr_launches = l0 + kGraphSteps / per;
     }
     while (done < nsteps) {
         const int k = nsteps - done >= per ? per : 1;
-        const hipError_t e = batch_launch_steps(b, k);
+        const hipError_t e =
+            batch_launch_steps(b, k, nullptr, b->steps_since_upload + done,
+                               (int)((b->launches_since_upload + launches) & 1));
         if (e != hipSuccess) {
             b->last_error = std::string("launching a batched step: ") + hipGetErrorString(e);
             return LBM_ERR_DEVICE;
@@ -1157,7 +1184,9 @@ lbm_status lbm_batch_autotune(lbm_batch *b, double out[3])
             b->bx = bx;
             b->rows = rows;
             if (batch_upload(b) != LBM_OK) continue;
-            const double us = time_launches(b->stream, 3, [&] { return run_batch(b); });
+            const double us =
+                time_launches(b->stream, 3,
+                              [&] { return batch_launch_steps(b, 1, nullptr, 0, 0); });
             if (us >= 0 && us < best1) {
                 best1 = us;
                 bx1 = bx;
@@ -1177,7 +1206,8 @@ lbm_status lbm_batch_autotune(lbm_batch *b, double out[3])
                 b->rows2 = rows;
                 if (batch_upload(b) != LBM_OK) continue;
                 const double us =
-                    0.5 * time_launches(b->stream, 3, [&] { return run_batch2(b); });
+                    0.5 * time_launches(b->stream, 3,
+                                        [&] { return batch_launch_steps(b, 2, nullptr, 0, 0); });
                 if (us >= 0 && us < best2) {
                     best2 = us;
                     bx2 = bx;

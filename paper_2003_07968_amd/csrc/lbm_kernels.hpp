@@ -130,22 +130,29 @@ struct Coeffs {
 };
 
 // The coefficients in the arithmetic type of a storage mode.
+// tr0, tr1, tr2: the trace M2_bb as tr0 psi_0 + tr1 (psi_1 + .. + psi_4) +
+// tr2 (psi_5 + .. + psi_8), the direct trace of Eq. SOMED (-8, 1, 1)/27 or
+// the alternative 2 cs^2 (M0 - psi_0) = (-10/27, 2/27, 1/54).
 template <class R>
 struct Phys {
     R omega, guo, eos_b, kcT, ka, invG, cSC, cA, cB, rho_ref, s_e, s_z, s_q;
-    int trace_alt;
+    R tr0, tr1, tr2;
     __device__ explicit Phys(const Coeffs &c)
         : omega((R)c.omega), guo((R)c.guo), eos_b((R)c.eos_b), kcT((R)c.kcT), ka((R)c.ka),
           invG((R)c.invG), cSC((R)c.cSC), cA((R)c.cA), cB((R)c.cB), rho_ref((R)c.rho_ref),
-          s_e((R)c.s_e), s_z((R)c.s_z), s_q((R)c.s_q), trace_alt(c.trace_alt)
+          s_e((R)c.s_e), s_z((R)c.s_z), s_q((R)c.s_q),
+          tr0(c.trace_alt ? R(-10.0 / 27.0) : R(-8.0 / 27.0)),
+          tr1(c.trace_alt ? R(2.0 / 27.0) : R(1.0 / 27.0)),
+          tr2(c.trace_alt ? R(1.0 / 54.0) : R(1.0 / 27.0))
     {
     }
 };
 
 // Tile decomposition of one sweep.  Strip s covers interior columns
-// [s * width, min(nx, (s + 1) * width)); width is a multiple of the storage's
-// store alignment (64-128 bytes) whenever the lattice needs more than one
-// strip, so the stores of neighbouring workgroups never share a cache line.
+// [s * width, min(nx, (s + 1) * width)); whenever the lattice needs more than
+// one strip, width is a multiple of 64 bytes of FP32 or FP16 or 128 bytes of
+// FP64 (single-step sweeps, so that the stores of neighbouring workgroups
+// never share a cache line) or of 16 columns (the two-step pass).
 struct Tiles {
     int nstrips, nseg, ntiles, width;
 };
@@ -254,10 +261,16 @@ __device__ __forceinline__ float root(float v) { return __builtin_amdgcn_sqrtf(v
 // deviations d_i = f_i - w_i rho_ref: rho = rho_ref + sum_i d_i.  Returns
 // false when the density is outside the EOS domain (with FORCE = 0, when it
 // is not positive and finite).
+template <class R>
+__device__ __forceinline__ R density(const R d[kQ], R ref)
+{
+    return ((((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8]) + ref;
+}
+
 template <int FORCE, class R>
 __device__ __forceinline__ bool rho_psi(const R d[kQ], R ref, const Phys<R> &P, R &rho, R &psi)
 {
-    rho = ((((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8]) + ref;
+    rho = density<R>(d, ref);
     if (!FORCE) {
         psi = R(0);
         return rho > R(0) && rho < R(INFINITY);
@@ -279,7 +292,11 @@ __device__ __forceinline__ unsigned long long domain_key(long long t, int r, int
 }
 
 // Force of Eq. IFT from s_i = psi(x + c_i) (Eqs. FOMED, SOMED, SCF,
-// DFTCCC, DFTCST).
+// DFTCCC, DFTCST).  The moments with the D2Q9 weights:
+//   M1_x = (s1 - s3)/9 + (s5 - s6 - s7 + s8)/36, M1_y likewise,
+//   M2_xx = -4/27 s0 + 2/27 (s1 + s3) - 1/27 (s2 + s4) + 1/54 (s5 + .. + s8),
+//   M2_yy likewise with x and y exchanged, M2_xy = (s5 - s6 + s7 - s8)/36,
+// each combination of psi values with multiply-adds.
 template <class R>
 __device__ __forceinline__ void force(const R s[kQ], const Phys<R> &P, R &Fx, R &Fy)
 {
@@ -287,15 +304,15 @@ __device__ __forceinline__ void force(const R s[kQ], const Phys<R> &P, R &Fx, R 
     const R s13 = s[1] + s[3], s24 = s[2] + s[4];
     const R a58 = s[5] - s[7], b68 = s[6] - s[8];
     const R s58 = (s[5] + s[6]) + (s[7] + s[8]);
-    const R M1x = d13 * R(1.0 / 9.0) + (a58 - b68) * R(1.0 / 36.0);
-    const R M1y = d24 * R(1.0 / 9.0) + (a58 + b68) * R(1.0 / 36.0);
-    const R M2xx = s[0] * R(-4.0 / 27.0) + s13 * R(2.0 / 27.0) - s24 * R(1.0 / 27.0) +
-                   s58 * R(1.0 / 54.0);
-    const R M2yy = s[0] * R(-4.0 / 27.0) - s13 * R(1.0 / 27.0) + s24 * R(2.0 / 27.0) +
-                   s58 * R(1.0 / 54.0);
+    const R M1x = fma(d13, R(1.0 / 9.0), (a58 - b68) * R(1.0 / 36.0));
+    const R M1y = fma(d24, R(1.0 / 9.0), (a58 + b68) * R(1.0 / 36.0));
+    const R q58 = s58 * R(1.0 / 54.0);
+    const R M2xx =
+        fma(s[0], R(-4.0 / 27.0), fma(s13, R(2.0 / 27.0), fma(s24, R(-1.0 / 27.0), q58)));
+    const R M2yy =
+        fma(s[0], R(-4.0 / 27.0), fma(s24, R(2.0 / 27.0), fma(s13, R(-1.0 / 27.0), q58)));
     const R M2xy = ((s[5] + s[7]) - (s[6] + s[8])) * R(1.0 / 36.0);
-    const R M0 = s[0] * R(4.0 / 9.0) + (s13 + s24) * R(1.0 / 9.0) + s58 * R(1.0 / 36.0);
-    const R tr = P.trace_alt ? R(2.0 / 3.0) * (M0 - s[0]) : M2xx + M2yy;
+    const R tr = fma(P.tr0, s[0], fma(P.tr1, s13 + s24, P.tr2 * s58));
     const R ax = fma(M1x, M2xx, M1y * M2xy);  // (M1 . M2)_x
     const R ay = fma(M1x, M2xy, M1y * M2yy);  // (M1 . M2)_y
     const R sc = P.cSC * s[0], tb = P.cB * tr;
@@ -832,23 +849,38 @@ __device__ __forceinline__ const BatchEntry &batch_entry(const BatchEntry *__res
     return table[lo];
 }
 
-// One time step of every lattice of a batch: workgroup b takes batch tile
-// xcd_tile(b) and runs tile b - tile0 of its lattice.  The steps and the
-// launches since the table was written are read from d_ctr[0] and d_ctr[1]
-// (so that a captured graph replays correctly): the first gives the time,
-// the parity of the second the source buffer.
-template <int BX, int PF, int FORCE, int ST, int COLL>
-__global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(const BatchEntry *__restrict__ table,
-                                                        int nlat,
-                                                        const long long *__restrict__ d_ctr)
+// Where a batched launch starts: the steps and the launches since the batch
+// table was written (the first gives the time, the parity of the second the
+// source buffer).  Eager launches pass them as arguments (d_ctr = nullptr);
+// launches captured in a graph add their position in the graph to counters
+// in device memory, d_ctr[0] steps and d_ctr[1] launches, which a one-thread
+// kernel at the end of the graph moves on, so that every replay starts where
+// the previous one ended.
+struct BatchPos {
+    long long steps;
+    int parity;
+};
+__device__ __forceinline__ BatchPos batch_pos(const long long *__restrict__ d_ctr,
+                                              long long steps_add, int launches_add)
 {
-    const long long steps = d_ctr[0];
-    const int parity = (int)(d_ctr[1] & 1);
+    const long long s0 = d_ctr ? d_ctr[0] : 0, l0 = d_ctr ? d_ctr[1] : 0;
+    return BatchPos{s0 + steps_add, (int)((l0 + launches_add) & 1)};
+}
+
+// One time step of every lattice of a batch: workgroup b takes batch tile
+// xcd_tile(b) and runs tile b - tile0 of its lattice; time and source buffer
+// from batch_pos.
+template <int BX, int PF, int FORCE, int ST, int COLL>
+__global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(
+    const BatchEntry *__restrict__ table, int nlat, const long long *__restrict__ d_ctr,
+    long long steps_add, int launches_add)
+{
+    const BatchPos pos = batch_pos(d_ctr, steps_add, launches_add);
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const BatchEntry &e = batch_entry<&BatchEntry::tile0>(table, nlat, b);
-    sweep_tile<BX, kStep, PF, FORCE, ST, COLL>(e.buf[parity], (void *)e.buf[parity ^ 1], e.c,
-                                               e.tl, b - e.tile0, e.t0 + steps, e.err, Fields{},
-                                               nullptr, nullptr);
+    sweep_tile<BX, kStep, PF, FORCE, ST, COLL>(e.buf[pos.parity], (void *)e.buf[pos.parity ^ 1],
+                                               e.c, e.tl, b - e.tile0, e.t0 + pos.steps, e.err,
+                                               Fields{}, nullptr, nullptr);
 }
 
 // Two time steps in one pass, t -> t + 2: the populations are read once and
@@ -876,10 +908,21 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(c
 // 3 (row r) three, 5 and 6 (row r - 1) four.  Populations 0, 2 and 4 come
 // from the own lane and stay in registers.  Register sets rotate with period 6
 // (the loop is unrolled six times).
-template <class R, int BX, bool LOC>
+//
+// Walk direction (FP64 storage, ALT): neighbouring segments walk in opposite
+// directions, as in the single-step sweep, so that the six rows two segments
+// share (three halo rows of each) are read by both near the same time, at
+// the start or at the end of both walks, and the second read comes from L2.
+// Walking down the lattice, the rows B pulls populations 2, 5, 6 from (row
+// r - 1) and 4, 7, 8 from (row r + 1) trade places in the hand-over rings,
+// so populations 4, 7, 8 get the longer rings of 2, 5, 6 (one more LDS row
+// pair, four more registers), and the two rows of the force stencil are
+// picked by direction.  The FP32-arithmetic modes, bound by instruction
+// issue rather than bandwidth, all walk up the lattice.
+template <class R, int BX, bool LOC, bool ALT>
 struct Pass2Lds {
     R psi_a[3][BX], psi_b[3][BX];  // psi of A's and B's rows
-    R p78[2][2][BX];               // populations 7, 8 of A's rows
+    R p78[ALT ? 4 : 2][2][BX];     // populations 7, 8 of A's rows
     R p13[3][2][BX];               // populations 1, 3
     R p56[4][2][BX];               // populations 5, 6
     // per-cell mode: the reference R of A's input rows (exchanged for the
@@ -888,27 +931,42 @@ struct Pass2Lds {
     float r_in[LOC ? 2 : 1][BX], r_out[LOC ? 4 : 1][BX];
 };
 
+// Segments that alternate their walk direction (see walk2).
+template <int ST>
+constexpr bool kAlt2 = ST == LBM_STORE_F64;
+
 template <int BX, int PF, int FORCE, int ST, int COLL>
 __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ src,
                                       typename Store<ST>::E *__restrict__ dst, const Coeffs &c,
-                                      long long t, int ys, int n, int x, const Cols &cols,
+                                      long long t, int y0, int dir, int n, int x, const Cols &cols,
                                       bool active, bool valid_b, bool interior,
-                                      Pass2Lds<typename Store<ST>::R, BX, Store<ST>::local> &L,
+                                      Pass2Lds<typename Store<ST>::R, BX, Store<ST>::local,
+                                               kAlt2<ST>> &L,
                                       unsigned long long &bad)
 {
     using E = typename Store<ST>::E;
     using R = typename Store<ST>::R;
     constexpr bool LOC = Store<ST>::local;
+    constexpr bool ALT = kAlt2<ST>;
     static_assert(PF == 1, "the period-6 rotation assumes one row of prefetch");
+    static_assert(!(ALT && LOC), "the per-cell mode walks up the lattice only");
     constexpr int K = PF + 2;
     const Phys<R> P(c);
     const R gref = (R)c.rho_ref;
     const int tx = threadIdx.x;
     const int txm = tx > 0 ? tx - 1 : 0, txp = tx < BX - 1 ? tx + 1 : BX - 1;
+    // walk position s is lattice row y0 + dir s (dir = +1, or -1 with ALT)
+    const bool fwd = !ALT || dir > 0;
+    const int ystep = fwd ? 1 : -1;
     auto lrow = [&](int s) {
-        const int r = (ys + s) % c.ny;
+        const int r = (y0 + ystep * s) % c.ny;
         return r < 0 ? r + c.ny : r;
     };
+    // psi ring slots of the rows on either side of the walk's current row,
+    // as lattice rows r - 1 (dn) and r + 1 (up), from the slots of the walk's
+    // previous (back) and next (ahead) rows
+    auto slot_dn = [&](int back, int ahead) { return fwd ? back : ahead; };
+    auto slot_up = [&](int back, int ahead) { return fwd ? ahead : back; };
     auto check = [&](bool ok, long long step, int s) {
         if (!ok) bad = min(bad, domain_key(step, lrow(s), x, c.nx));
     };
@@ -919,7 +977,8 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
 
     R fa[K][kQ];
     R rho_a[2], rho_b[2];   // rho of the last two psi rows of each step
-    R h0[3], h2[6], h4[2];  // populations 0, 2, 4 of A's last post-collision rows
+    // populations 0, 2, 4 of A's last post-collision rows
+    R h0[3], h2[6], h4[ALT ? 6 : 2];
     // per-cell mode: R triples of A's input rows (slot = (row + 1) mod 3), R
     // of A's rows before their collision, R of the next rows in flight
     Tri<R> ta[3];
@@ -943,7 +1002,10 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
 #pragma unroll
     for (int k = 0; k < 6; ++k)
         h2[k] = R(0);
-    h0[0] = h0[1] = h0[2] = h4[0] = h4[1] = R(0);
+    h0[0] = h0[1] = h0[2] = R(0);
+#pragma unroll
+    for (int k = 0; k < (ALT ? 6 : 2); ++k)
+        h4[k] = R(0);
     ra[0] = ra[1] = R(0);
     // prologue: A's populations of rows -3 .. -4 + PF
 #pragma unroll
@@ -1002,16 +1064,17 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
         if constexpr (DO_A) {
             R Fx = R(0), Fy = R(0);
             if (FORCE) {
-                const Row<R> T = psi_row(L.psi_a, (J + 1) % 3);
+                // walk rows m - 5 (back), m - 4 (current), m - 3 (ahead)
+                const Row<R> D = psi_row(L.psi_a, slot_dn((J + 1) % 3, J % 3));
                 const Row<R> C = psi_row(L.psi_a, (J + 2) % 3);
-                const Row<R> U = psi_row(L.psi_a, J % 3);
+                const Row<R> U = psi_row(L.psi_a, slot_up((J + 1) % 3, J % 3));
                 R sv[kQ];
-                stencil<+1, R>(T, C, U, sv);
+                stencil<+1, R>(D, C, U, sv);
                 force<R>(sv, P, Fx, Fy);
             }
             R *g = fa[a_cur];
-            const R rho = rho_a[(J + 1) % 2];
             const R ref_cur = LOC ? ra[(J + 1) % 2] : gref;
+            const R rho = rho_a[(J + 1) % 2];
             R ux, uy;
             velocity<R>(g, rho, Fx, Fy, ux, uy);
             if constexpr (COLL == LBM_COLL_MRT)
@@ -1038,13 +1101,13 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
             auto rd = [&](int i) { return LOC ? g[i] : (R)(E)g[i]; };
             h0[J % 3] = rd(0);
             h2[J] = rd(2);
-            h4[J % 2] = rd(4);
+            h4[ALT ? J : J % 2] = rd(4);
             L.p13[J % 3][0][tx] = rd(1);
             L.p13[J % 3][1][tx] = rd(3);
             L.p56[m & 3][0][tx] = rd(5);
             L.p56[m & 3][1][tx] = rd(6);
-            L.p78[J % 2][0][tx] = rd(7);
-            L.p78[J % 2][1][tx] = rd(8);
+            L.p78[ALT ? (m & 3) : J % 2][0][tx] = rd(7);
+            L.p78[ALT ? (m & 3) : J % 2][1][tx] = rd(8);
         }
         __syncthreads();
         // B's pulled populations of row m - 5 - back (back = 0: the row turned
@@ -1052,18 +1115,33 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
         // at iteration q + 4
         auto pull_b = [&](auto backc, R g[kQ]) {
             constexpr int b = decltype(backc)::value;
-            constexpr int s2 = (J + 2 - b) % 2, s3r = (J + 5 - b) % 3, s6 = (J + 10 - b) % 6;
-            const int s4 = (m + 2 - b) & 3;
-            // row r + 1 (written at m - b), row r (m - 1 - b), row r - 1 (m - 2 - b)
-            g[4] = h4[s2];
-            g[7] = L.p78[s2][0][txp];
-            g[8] = L.p78[s2][1][txm];
+            constexpr int s3r = (J + 5 - b) % 3;
+            // walk rows: ahead (written at m - b), current (m - 1 - b), back
+            // (m - 2 - b); populations 4, 7, 8 come from lattice row r + 1,
+            // 2, 5, 6 from r - 1
+            if constexpr (ALT) {
+                constexpr int h_ahead = (J + 6 - b) % 6, h_back = (J + 4 - b) % 6;
+                const int l_ahead = (m - b) & 3, l_back = (m + 2 - b) & 3;
+                const int l78 = fwd ? l_ahead : l_back, l56 = fwd ? l_back : l_ahead;
+                g[4] = fwd ? h4[h_ahead] : h4[h_back];
+                g[2] = fwd ? h2[h_back] : h2[h_ahead];
+                g[7] = L.p78[l78][0][txp];
+                g[8] = L.p78[l78][1][txm];
+                g[5] = L.p56[l56][0][txm];
+                g[6] = L.p56[l56][1][txp];
+            } else {
+                constexpr int s2 = (J + 2 - b) % 2, s6 = (J + 10 - b) % 6;
+                const int s4 = (m + 2 - b) & 3;
+                g[4] = h4[s2];
+                g[7] = L.p78[s2][0][txp];
+                g[8] = L.p78[s2][1][txm];
+                g[2] = h2[s6];
+                g[5] = L.p56[s4][0][txm];
+                g[6] = L.p56[s4][1][txp];
+            }
             g[0] = h0[s3r];
             g[1] = L.p13[s3r][0][txm];
             g[3] = L.p13[s3r][1][txp];
-            g[2] = h2[s6];
-            g[5] = L.p56[s4][0][txm];
-            g[6] = L.p56[s4][1][txp];
         };
         // step B: rho and psi of row m - 5
         if constexpr (DO_BPSI) {
@@ -1095,11 +1173,12 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
             }
             R Fx = R(0), Fy = R(0);
             if (FORCE) {
-                const Row<R> T = psi_row(L.psi_b, (J + 1) % 3);
+                // walk rows m - 7 (back), m - 6 (current), m - 5 (ahead)
+                const Row<R> D = psi_row(L.psi_b, slot_dn((J + 1) % 3, J % 3));
                 const Row<R> C = psi_row(L.psi_b, (J + 2) % 3);
-                const Row<R> U = psi_row(L.psi_b, J % 3);
+                const Row<R> U = psi_row(L.psi_b, slot_up((J + 1) % 3, J % 3));
                 R sv[kQ];
-                stencil<+1, R>(T, C, U, sv);
+                stencil<+1, R>(D, C, U, sv);
                 force<R>(sv, P, Fx, Fy);
             }
             const R rho = rho_b[(J + 1) % 2];
@@ -1159,10 +1238,13 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
 // Halo columns of the two-step pass on each side of its output strip.
 constexpr int kHalo2 = 3;
 
-// Waves per SIMD the two-step pass is compiled for.  FP64 runs at two (173
-// VGPRs with BGK; bounding it to three waves spilled 8 registers and measured
-// 2-4% slower); the FP32-arithmetic modes fit four.
-template <int ST, int COLL>
+// Waves per SIMD the two-step pass is compiled for.  FP64 runs at two (172
+// VGPRs with BGK).  Three fit without spills when the density is recomputed
+// at the collision instead of kept from the psi phase (166 VGPRs, 50 kB of
+// LDS per workgroup), but measured slower on 2048^2: 140.6 us per launch in
+// whole rounds of 25-row segments against 134.4 us, the pass being close to
+// the HBM bandwidth it reaches.  The FP32-arithmetic modes fit four.
+template <int ST>
 constexpr int kWaves2 = ST == LBM_STORE_F64 ? 2 : 4;
 
 // One tile of the two-step pass: output strip `strip` of row band `seg`.
@@ -1174,7 +1256,7 @@ __device__ __forceinline__ void sweep2_tile(const void *__restrict__ src_v,
 {
     using E = typename Store<ST>::E;
     using R = typename Store<ST>::R;
-    __shared__ Pass2Lds<R, BX, Store<ST>::local> lds;
+    __shared__ Pass2Lds<R, BX, Store<ST>::local, kAlt2<ST>> lds;
     const int seg = tile / tl.nstrips;
     const int strip = tile - seg * tl.nstrips;
     const int xs = strip * tl.width;
@@ -1192,14 +1274,17 @@ __device__ __forceinline__ void sweep2_tile(const void *__restrict__ src_v,
     constexpr uint32_t es = sizeof(E);
     const Cols cols{(uint32_t)x * es, (uint32_t)xm * es, (uint32_t)xp * es};
     unsigned long long bad = ~0ull;
-    walk2<BX, PF, FORCE, ST, COLL>((const E *)src_v, (E *)dst_v, c, t, ys, ye - ys, x, cols, active,
-                                   valid_b, interior, lds, bad);
+    // odd segments walk down the lattice (FP64 storage; see walk2)
+    const int dir = (kAlt2<ST> && (seg & 1)) ? -1 : 1;
+    const int y0 = dir > 0 ? ys : ye - 1;
+    walk2<BX, PF, FORCE, ST, COLL>((const E *)src_v, (E *)dst_v, c, t, y0, dir, ye - ys, x, cols,
+                                   active, valid_b, interior, lds, bad);
     if (bad != ~0ull) atomicMin(err, bad);
 }
 
 // The two-step pass over one lattice.
 template <int BX, int PF, int FORCE, int ST, int COLL>
-__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST, COLL>)))
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST>)))
 void sweep2_kernel(const void *__restrict__ src, void *__restrict__ dst, Coeffs c, Tiles tl,
                    long long t, unsigned long long *__restrict__ err)
 {
@@ -1209,16 +1294,15 @@ void sweep2_kernel(const void *__restrict__ src, void *__restrict__ dst, Coeffs 
 // The two-step pass over every lattice of a batch (tiles and counters as in
 // batch_step_kernel; a launch advances two steps and swaps the buffers once).
 template <int BX, int PF, int FORCE, int ST, int COLL>
-__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST, COLL>)))
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST>)))
 void batch2_kernel(const BatchEntry *__restrict__ table, int nlat,
-                   const long long *__restrict__ d_ctr)
+                   const long long *__restrict__ d_ctr, long long steps_add, int launches_add)
 {
-    const long long steps = d_ctr[0];
-    const int parity = (int)(d_ctr[1] & 1);
+    const BatchPos pos = batch_pos(d_ctr, steps_add, launches_add);
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const BatchEntry &e = batch_entry<&BatchEntry::tile0_2>(table, nlat, b);
-    sweep2_tile<BX, PF, FORCE, ST, COLL>(e.buf[parity], (void *)e.buf[parity ^ 1], e.c, e.tl2,
-                                         b - e.tile0_2, e.t0 + steps, e.err);
+    sweep2_tile<BX, PF, FORCE, ST, COLL>(e.buf[pos.parity], (void *)e.buf[pos.parity ^ 1], e.c,
+                                         e.tl2, b - e.tile0_2, e.t0 + pos.steps, e.err);
 }
 
 // pull storage: the deviation from w_i rho_ref rounded once, or in the
@@ -1346,11 +1430,14 @@ struct SweepArgs {
     hipStream_t stream;
 };
 
-// Arguments of a batched launch.
+// Arguments of a batched launch: where it starts (batch_pos: counters in
+// device memory, or nullptr, plus the steps and launches to add).
 struct BatchArgs {
     const BatchEntry *table;
     int nlat;
     const long long *ctr;
+    long long steps_add;
+    int launches_add;
     int bx;
     unsigned grid;
     int force_on, coll;
@@ -1436,7 +1523,8 @@ hipError_t batch_launch_bx(const BatchArgs &a)
 #define LBM_CASE(BX)                                                                          \
     case BX:                                                                                  \
         hipLaunchKernelGGL((batch_step_kernel<BX, kPrefetch, FORCE, ST, COLL>), dim3(a.grid),  \
-                           dim3(BX), 0, a.stream, a.table, a.nlat, a.ctr);                    \
+                           dim3(BX), 0, a.stream, a.table, a.nlat, a.ctr, a.steps_add,        \
+                           a.launches_add);                                                   \
         break;
         LBM_WIDTHS1(LBM_CASE)
 #undef LBM_CASE
@@ -1463,7 +1551,7 @@ hipError_t batch2_launch_bx(const BatchArgs &a)
 #define LBM_CASE(BX)                                                                          \
     case BX:                                                                                  \
         hipLaunchKernelGGL((batch2_kernel<BX, 1, FORCE, ST, COLL>), dim3(a.grid), dim3(BX), 0, \
-                           a.stream, a.table, a.nlat, a.ctr);                                 \
+                           a.stream, a.table, a.nlat, a.ctr, a.steps_add, a.launches_add);    \
         break;
         LBM_WIDTHS2(LBM_CASE)
 #undef LBM_CASE

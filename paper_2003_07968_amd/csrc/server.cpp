@@ -24,6 +24,9 @@ namespace {
 constexpr int kStorages = 4;
 // one batch per (storage mode, force switch, collision operator)
 constexpr int kBatchKeys = kStorages * 2 * 2;
+// Rounds between checks of the resident jobs' sticky errors when no job
+// retires (a round that retires jobs checks them anyway).
+constexpr int kErrorCheckRounds = 16;
 
 struct Job {
     int64_t id;
@@ -59,6 +62,7 @@ struct lbm_server {
     std::vector<std::pair<int64_t, int32_t>> done;
     int64_t next_id = 0, submitted = 0, completed = 0, rounds = 0, cell_steps = 0;
     size_t table_bytes = 0;  // arena bytes held by the batch tables
+    int rounds_since_check = 0;
     bool broken = false;
 };
 
@@ -203,6 +207,30 @@ lbm_status retire(lbm_server *s, int32_t *n_retired)
     return LBM_OK;
 }
 
+// Retire, with their error, the resident jobs whose lattice has left the EOS
+// domain (each one's sticky error word, read after the stream has drained),
+// so that a failed job stops holding its slot and memory.
+lbm_status retire_failed(lbm_server *s, int32_t *n_retired)
+{
+    int32_t n = 0;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_ERR_DEVICE;
+    for (size_t k = 0; k < s->resident.size();) {
+        Job *j = s->resident[k];
+        const lbm_status st = lbm_sync(j->h);
+        if (st == LBM_OK) {
+            ++k;
+            continue;
+        }
+        if (st != LBM_ERR_DOMAIN) return LBM_ERR_DEVICE;
+        s->resident.erase(s->resident.begin() + (long)k);
+        if (lbm_batch_remove(s->batches[j->key], j->h) != LBM_OK) return LBM_ERR_DEVICE;
+        finish(s, j, st);
+        ++n;
+    }
+    if (n_retired) *n_retired = n;
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -282,14 +310,22 @@ lbm_status lbm_server_advance(lbm_server *s, int32_t *n_retired)
     if (!s) return LBM_ERR_INVALID_ARG;
     if (s->broken) return LBM_ERR_DEVICE;
     // jobs admitted with nothing left to do (nsteps = 0) leave before the
-    // batched step, which advances every member of a batch
-    int32_t early = 0, late = 0;
+    // batched step, which advances every member of a batch.  The round returns
+    // as soon as its work is enqueued: the stream is waited for only to copy
+    // out the results of retiring jobs and, in such rounds and every
+    // kErrorCheckRounds rounds, to find jobs that failed, so the host prepares
+    // the next rounds while the device runs this one.
+    int32_t early = 0, late = 0, failed = 0;
     lbm_status st = admit(s);
     if (st == LBM_OK) st = retire(s, &early);
     if (st == LBM_OK) st = step_batches(s);
     if (st == LBM_OK) st = retire(s, &late);
-    if (n_retired) *n_retired = early + late;
-    if (st == LBM_OK && hipStreamSynchronize(s->stream) != hipSuccess) st = LBM_ERR_DEVICE;
+    if (st == LBM_OK &&
+        (early + late > 0 || ++s->rounds_since_check >= kErrorCheckRounds)) {
+        st = retire_failed(s, &failed);
+        s->rounds_since_check = 0;
+    }
+    if (n_retired) *n_retired = early + late + failed;
     if (st != LBM_OK) {
         s->broken = true;
         return LBM_ERR_DEVICE;
@@ -328,6 +364,9 @@ lbm_status lbm_server_get_stats(const lbm_server *s, lbm_server_stats *out)
 void lbm_server_destroy(lbm_server *s)
 {
     if (!s) return;
+    // work still queued on the stream uses the arena; let it finish before the
+    // caller may free it
+    (void)hipStreamSynchronize(s->stream);
     for (Job *j : s->resident) {
         if (j->h) lbm_destroy(j->h);
         delete j;

@@ -410,6 +410,10 @@ class Lattice:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         assert self.workspace.data_ptr() % _ALIGN == 0
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        if self.stream != torch.cuda.current_stream(device):
+            # the library's work runs on self.stream: keep the caching allocator
+            # from reusing the workspace before that work is done
+            self.workspace.record_stream(self.stream)
 
         def dev(a):
             if a is None:
@@ -417,6 +421,10 @@ class Lattice:
             t = torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
             return t
         self._rho0, self._ux0, self._uy0 = dev(rho0), dev(ux0), dev(uy0)
+        if self.stream != torch.cuda.current_stream(device):
+            for t in (self._rho0, self._ux0, self._uy0):
+                if t is not None:
+                    t.record_stream(self.stream)
         self.handle = lbm_init(self.params, self.workspace, self._rho0, self._ux0, self._uy0,
                                self.stream)
 
@@ -485,6 +493,8 @@ class Batch:
         self.workspace = torch.empty(lbm_batch_workspace_bytes(capacity), dtype=torch.uint8,
                                      device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        if self.stream != torch.cuda.current_stream(device):
+            self.workspace.record_stream(self.stream)
         self.handle = lbm_batch_create(capacity, self.workspace, self.stream)
         self.members = []
 
@@ -532,6 +542,9 @@ class Server:
                  stream=None):
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device)
+        # the server's work runs on its own stream, which the caching allocator
+        # must wait for before it reuses the arena
+        self.arena.record_stream(self.stream)
         self.handle = lbm_server_create(max_resident, quantum, max_bypass, self.arena,
                                         self.stream)
         self._outputs = {}
@@ -559,7 +572,7 @@ class Server:
 
     def close(self):
         if self.handle:
-            lbm_server_destroy(self.handle)
+            lbm_server_destroy(self.handle)   # waits for the server's stream
             self.handle = None
 
     def __del__(self):

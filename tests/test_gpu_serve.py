@@ -169,3 +169,28 @@ def test_domain_error_reported_for_its_job_only():
         p, r, n = jobs[k]
         with torch.cuda.stream(srv.stream):
             assert np.array_equal(rho, _alone(p, r, n)[0])
+
+
+def test_failed_job_leaves_early():
+    # a job that leaves the EOS domain at its first step but asks for a
+    # million steps is retired with its error within a few check intervals
+    # (16 rounds), not after its step count; the other jobs are unaffected
+    require_gpu()
+    jobs = _jobs(2, seed=15, storages=("f64",), sides=(24, 40), steps=(40, 60))
+    p, r, _ = jobs[0]
+    r = r.copy()
+    r[3, 4] = 0.95   # outside the EOS domain
+    srv = lbm.Server(arena_bytes=64 << 20, max_resident=4, quantum=5)
+    bad = srv.submit(p, r, 1_000_000)
+    good = srv.submit(*jobs[1])
+    results, rounds = {}, 0
+    while len(results) < 2:
+        srv.advance()
+        rounds += 1
+        for job, st, rho, f in srv.poll():
+            results[job] = (st, rounds)
+        assert rounds < 100, "the failed job was not retired early"
+    log(f"  failed job retired after {results[bad][1]} rounds, the other after {results[good][1]}")
+    assert results[bad][0] == lbm.LBM_ERR_DOMAIN
+    assert results[good][0] == lbm.LBM_OK
+    assert srv.stats()["resident"] == 0
