@@ -169,8 +169,8 @@ __device__ __forceinline__ int wrap_hi(int v, int n) { return v >= n ? v - n : v
 
 // Pulled populations of row r at column x: f_i(x, r) = X_i(x - c_ix, r - c_iy).
 // Row bases are uniform across the workgroup (scalar registers) and the
-// column enters as a 32-bit byte offset, so each load is a single
-// scalar-base + vector-offset global load.
+// column enters as a 32-bit byte offset, so each load and store is a single
+// scalar-base + vector-offset global access.
 struct Cols {
     uint32_t o, m, p;  // byte offsets of columns x, x - 1 (wrapped), x + 1 (wrapped)
 };
@@ -179,6 +179,23 @@ template <class E, class R>
 __device__ __forceinline__ R ld(const E *__restrict__ row, uint32_t byte_off)
 {
     return (R) * (const E *)((const char *)row + byte_off);
+}
+
+// Row r of the per-cell mode's reference block.
+__device__ __forceinline__ float *ref_row(const void *base, const Coeffs &c, int r)
+{
+    return (float *)((char *)base + c.r_off) + (size_t)r * c.r_pitch;
+}
+
+// The nine populations of one cell to row y of the storage (nontemporal).
+template <class E>
+__device__ __forceinline__ void store_pops(E *__restrict__ dst, const Coeffs &c, int y,
+                                           uint32_t col, const E v[kQ])
+{
+    E *row = dst + (size_t)y * c.pitch;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+        __builtin_nontemporal_store(v[i], (E *)((char *)(row + i * c.plane) + col));
 }
 
 // The stored values X_i of the pulled populations, as R.  For the shifted
@@ -223,7 +240,7 @@ template <class R>
 __device__ __forceinline__ RefPair<R> load_ref(const void *__restrict__ src, const Coeffs &c,
                                                int r, const Cols &x, bool first)
 {
-    const float *row = (const float *)((const char *)src + c.r_off) + (size_t)r * c.r_pitch;
+    const float *row = ref_row(src, c, r);
     return RefPair<R>{ld<float, R>(row, 2 * x.o), ld<float, R>(row, 2 * (first ? x.m : x.p))};
 }
 
@@ -670,7 +687,6 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
             else
                 collide<R>(f[cur], ref_cur, C.rho, ux, uy, Fx, Fy, P);
             if (interior) {
-                const size_t prow = (size_t)y * c.pitch;
                 if constexpr (Store<ST>::local) {
                     // per-cell reference: the new R = sum_i f*_i = ref + s with
                     // s = sum_i d*_i, X_i = round(f*_i - w_i R) = round(d*_i - w_i s),
@@ -681,23 +697,23 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
                         (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) +
                         g[8];
                     R err = R(0);
+                    E X[kQ];
 #pragma unroll
                     for (int i = 0; i < kQ; ++i) {
                         const R w = i == 0 ? R(4.0 / 9.0) : (i < 5 ? R(1.0 / 9.0) : R(1.0 / 36.0));
                         const R dev = fma(-w, sd, g[i]);
-                        const E X = (E)dev;
-                        err += dev - (R)X;
-                        __builtin_nontemporal_store(
-                            X, (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                        X[i] = (E)dev;
+                        err += dev - (R)X[i];
                     }
-                    float *rrow = (float *)((char *)dst + c.r_off) + (size_t)y * c.r_pitch;
+                    store_pops<E>(dst, c, y, cols.o, X);
                     __builtin_nontemporal_store((float)(ref_cur + (sd + err)),
-                                                (float *)((char *)rrow + 2 * cols.o));
+                                                (float *)((char *)ref_row(dst, c, y) + 2 * cols.o));
                 } else {
+                    E X[kQ];
 #pragma unroll
                     for (int i = 0; i < kQ; ++i)
-                        __builtin_nontemporal_store(
-                            (E)f[cur][i], (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                        X[i] = (E)f[cur][i];
+                    store_pops<E>(dst, c, y, cols.o, X);
                 }
             }
         } else if (MODE == kMoments) {
@@ -918,7 +934,9 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(
 // so populations 4, 7, 8 get the longer rings of 2, 5, 6 (one more LDS row
 // pair, four more registers), and the two rows of the force stencil are
 // picked by direction.  The FP32-arithmetic modes, bound by instruction
-// issue rather than bandwidth, all walk up the lattice.
+// issue rather than bandwidth, all walk up the lattice: alternating cuts
+// their re-read halo traffic too, but the longer rings cost them more issue
+// time than the traffic saves (2 to 3 % per launch, measured).
 template <class R, int BX, bool LOC, bool ALT>
 struct Pass2Lds {
     R psi_a[3][BX], psi_b[3][BX];  // psi of A's and B's rows
@@ -1191,30 +1209,29 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
             const int sb = m - 6;
             if (interior && sb >= 0 && sb < n) {
                 const int yb = lrow(sb);
-                const size_t prow = (size_t)yb * c.pitch;
                 if constexpr (LOC) {
                     // as the single-step store of the per-cell mode
                     const R sd =
                         (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) +
                         g[8];
                     R err = R(0);
+                    E X[kQ];
 #pragma unroll
                     for (int i = 0; i < kQ; ++i) {
                         const R w = i == 0 ? R(4.0 / 9.0) : (i < 5 ? R(1.0 / 9.0) : R(1.0 / 36.0));
                         const R dev = fma(-w, sd, g[i]);
-                        const E X = (E)dev;
-                        err += dev - (R)X;
-                        __builtin_nontemporal_store(
-                            X, (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                        X[i] = (E)dev;
+                        err += dev - (R)X[i];
                     }
-                    float *rrow = (float *)((char *)dst + c.r_off) + (size_t)yb * c.r_pitch;
+                    store_pops<E>(dst, c, yb, cols.o, X);
                     __builtin_nontemporal_store((float)(ref_cur + (sd + err)),
-                                                (float *)((char *)rrow + 2 * cols.o));
+                                                (float *)((char *)ref_row(dst, c, yb) + 2 * cols.o));
                 } else {
+                    E X[kQ];
 #pragma unroll
                     for (int i = 0; i < kQ; ++i)
-                        __builtin_nontemporal_store(
-                            (E)g[i], (E *)((char *)(dst + i * c.plane + prow) + cols.o));
+                        X[i] = (E)g[i];
+                    store_pops<E>(dst, c, yb, cols.o, X);
                 }
             }
         }
