@@ -136,14 +136,24 @@ struct Coeffs {
 template <class R>
 struct Phys {
     R omega, guo, eos_b, kcT, ka, invG, cSC, cA, cB, rho_ref, s_e, s_z, s_q;
-    R tr0, tr1, tr2;
+    // Products of the coefficients above that the per-cell arithmetic uses,
+    // formed once in FP64 and rounded to R (see rho_psi, force, collide).
+    R g_kcT, g_ka, g_third;          // kcT/G, ka/G, 1/(3G)
+    R m2_0, m2_1, m2_2, m2_58, m2_xy; // cA/9 times the M2 weights of s0, -s24, s13, s58, s5-s6
+    R t0, t1, t2;                     // (cSC + cB tr0)/9, cB tr1/9, cB tr2/9
+    R keep, om3, g3;                  // 1 - omega, omega/3, guo/3
     __device__ explicit Phys(const Coeffs &c)
         : omega((R)c.omega), guo((R)c.guo), eos_b((R)c.eos_b), kcT((R)c.kcT), ka((R)c.ka),
           invG((R)c.invG), cSC((R)c.cSC), cA((R)c.cA), cB((R)c.cB), rho_ref((R)c.rho_ref),
-          s_e((R)c.s_e), s_z((R)c.s_z), s_q((R)c.s_q),
-          tr0(c.trace_alt ? R(-10.0 / 27.0) : R(-8.0 / 27.0)),
-          tr1(c.trace_alt ? R(2.0 / 27.0) : R(1.0 / 27.0)),
-          tr2(c.trace_alt ? R(1.0 / 54.0) : R(1.0 / 27.0))
+          s_e((R)c.s_e), s_z((R)c.s_z), s_q((R)c.s_q), g_kcT((R)(c.kcT * c.invG)),
+          g_ka((R)(c.ka * c.invG)), g_third((R)(c.invG / 3.0)),
+          m2_0((R)(c.cA * (-4.0 / 243.0))), m2_1((R)(c.cA * (-1.0 / 243.0))),
+          m2_2((R)(c.cA * (2.0 / 243.0))), m2_58((R)(c.cA / 486.0)),
+          m2_xy((R)(c.cA / 324.0)),
+          t0((R)((c.cSC + c.cB * (c.trace_alt ? -10.0 / 27.0 : -8.0 / 27.0)) / 9.0)),
+          t1((R)(c.cB * (c.trace_alt ? 2.0 / 27.0 : 1.0 / 27.0) / 9.0)),
+          t2((R)(c.cB * (c.trace_alt ? 1.0 / 54.0 : 1.0 / 27.0) / 9.0)),
+          keep((R)(1.0 - c.omega)), om3((R)(c.omega / 3.0)), g3((R)(c.guo / 3.0))
     {
     }
 };
@@ -175,10 +185,21 @@ struct Cols {
     uint32_t o, m, p;  // byte offsets of columns x, x - 1 (wrapped), x + 1 (wrapped)
 };
 
+// The column's byte offset, passed through an empty asm statement at each
+// access.  Left alone, the compiler widens the loop-invariant offset to 64
+// bits once, before the row loop, and then forms every address with a 64-bit
+// vector add instead of the scalar-base + 32-bit vector-offset form of the
+// global load and store (nine vector adds per row and step).
+__device__ __forceinline__ uint32_t col_offset(uint32_t o)
+{
+    asm("" : "+v"(o));
+    return o;
+}
+
 template <class E, class R>
 __device__ __forceinline__ R ld(const E *__restrict__ row, uint32_t byte_off)
 {
-    return (R) * (const E *)((const char *)row + byte_off);
+    return (R) * (const E *)((const char *)row + col_offset(byte_off));
 }
 
 // Row r of the per-cell mode's reference block.
@@ -195,7 +216,7 @@ __device__ __forceinline__ void store_pops(E *__restrict__ dst, const Coeffs &c,
     E *row = dst + (size_t)y * c.pitch;
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-        __builtin_nontemporal_store(v[i], (E *)((char *)(row + i * c.plane) + col));
+        __builtin_nontemporal_store(v[i], (E *)((char *)(row + i * c.plane) + col_offset(col)));
 }
 
 // The stored values X_i of the pulled populations, as R.  For the shifted
@@ -292,11 +313,13 @@ __device__ __forceinline__ bool rho_psi(const R d[kQ], R ref, const Phys<R> &P, 
         psi = R(0);
         return rho > R(0) && rho < R(INFINITY);
     }
+    // rad = (p(rho) - rho/3)/G with p = kcT rho num/(1 - br)^3 - ka rho^2,
+    // as rho (kcT/G num/(1 - br)^3 - (ka/G rho + 1/(3G)))
     const R br = P.eos_b * rho;
-    const R num = fma(br, fma(br, R(1) - br, R(1)), R(1));  // 1 + br + br^2 - br^3
     const R om = R(1) - br;
-    const R pr = fma(P.kcT * rho, quot(num, om * om * om), -P.ka * rho * rho);
-    const R rad = fma(rho, R(-1.0 / 3.0), pr) * P.invG;
+    const R num = fma(br, fma(br, om, R(1)), R(1));  // 1 + br + br^2 - br^3
+    const R lin = fma(P.g_ka, rho, P.g_third);
+    const R rad = rho * fma(P.g_kcT, quot(num, om * om * om), -lin);
     psi = root(rad);
     return rho > R(0) && br < R(1) && rad >= R(0) && rad < R(INFINITY);
 }
@@ -313,40 +336,45 @@ __device__ __forceinline__ unsigned long long domain_key(long long t, int r, int
 //   M1_x = (s1 - s3)/9 + (s5 - s6 - s7 + s8)/36, M1_y likewise,
 //   M2_xx = -4/27 s0 + 2/27 (s1 + s3) - 1/27 (s2 + s4) + 1/54 (s5 + .. + s8),
 //   M2_yy likewise with x and y exchanged, M2_xy = (s5 - s6 + s7 - s8)/36,
-// each combination of psi values with multiply-adds.
+//   tr = tr0 s0 + tr1 (s1 + .. + s4) + tr2 (s5 + .. + s8) (the trace of M2,
+//   either Eq. SOMED's or the alternative weights),
+//   F_a = cSC s0 M1_a + cA M1_b M2_ab + cB tr M1_a.
+// Evaluated as F_a = G0 N_a + N_b Q_ab with N = 9 M1 = (s1 - s3) + (a - b)/4,
+// Q = cA M2/9 and G0 = (cSC s0 + cB tr)/9, the constant factors folded into
+// the weights (Phys), each combination of psi values with multiply-adds.
 template <class R>
 __device__ __forceinline__ void force(const R s[kQ], const Phys<R> &P, R &Fx, R &Fy)
 {
     const R d13 = s[1] - s[3], d24 = s[2] - s[4];
     const R s13 = s[1] + s[3], s24 = s[2] + s[4];
-    const R a58 = s[5] - s[7], b68 = s[6] - s[8];
-    const R s58 = (s[5] + s[6]) + (s[7] + s[8]);
-    const R M1x = fma(d13, R(1.0 / 9.0), (a58 - b68) * R(1.0 / 36.0));
-    const R M1y = fma(d24, R(1.0 / 9.0), (a58 + b68) * R(1.0 / 36.0));
-    const R q58 = s58 * R(1.0 / 54.0);
-    const R M2xx =
-        fma(s[0], R(-4.0 / 27.0), fma(s13, R(2.0 / 27.0), fma(s24, R(-1.0 / 27.0), q58)));
-    const R M2yy =
-        fma(s[0], R(-4.0 / 27.0), fma(s24, R(2.0 / 27.0), fma(s13, R(-1.0 / 27.0), q58)));
-    const R M2xy = ((s[5] + s[7]) - (s[6] + s[8])) * R(1.0 / 36.0);
-    const R tr = fma(P.tr0, s[0], fma(P.tr1, s13 + s24, P.tr2 * s58));
-    const R ax = fma(M1x, M2xx, M1y * M2xy);  // (M1 . M2)_x
-    const R ay = fma(M1x, M2xy, M1y * M2yy);  // (M1 . M2)_y
-    const R sc = P.cSC * s[0], tb = P.cB * tr;
-    Fx = fma(sc, M1x, fma(P.cA, ax, tb * M1x));
-    Fy = fma(sc, M1y, fma(P.cA, ay, tb * M1y));
+    const R a57 = s[5] - s[7], b68 = s[6] - s[8];
+    const R p57 = s[5] + s[7], p68 = s[6] + s[8];
+    const R s58 = p57 + p68;
+    const R Nx = fma(R(0.25), a57 - b68, d13);
+    const R Ny = fma(R(0.25), a57 + b68, d24);
+    const R q0 = fma(P.m2_0, s[0], P.m2_58 * s58);
+    const R Qxx = fma(P.m2_2, s13, fma(P.m2_1, s24, q0));
+    const R Qyy = fma(P.m2_2, s24, fma(P.m2_1, s13, q0));
+    const R Qxy = (p57 - p68) * P.m2_xy;
+    const R G0 = fma(P.t0, s[0], fma(P.t1, s13 + s24, P.t2 * s58));
+    Fx = fma(G0, Nx, fma(Nx, Qxx, Ny * Qxy));
+    Fy = fma(G0, Ny, fma(Nx, Qxy, Ny * Qyy));
 }
 
 // Velocity (Eq. FMD).  The w_i rho_ref parts of the populations carry no
 // momentum, so the deviations give sum_i f_i c_i directly.
+// J = rho u = sum_i f_i c_i + F/2 is returned too.
 template <class R>
-__device__ __forceinline__ void velocity(const R d[kQ], R rho, R Fx, R Fy, R &ux, R &uy)
+__device__ __forceinline__ void velocity(const R d[kQ], R rho, R Fx, R Fy, R &ux, R &uy, R &Jx,
+                                         R &Jy)
 {
     const R jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]);
     const R jy = ((d[2] - d[4]) + (d[5] + d[6])) - (d[7] + d[8]);
     const R inv = recip(rho);
-    ux = (jx + R(0.5) * Fx) * inv;
-    uy = (jy + R(0.5) * Fy) * inv;
+    Jx = fma(R(0.5), Fx, jx);
+    Jy = fma(R(0.5), Fy, jy);
+    ux = Jx * inv;
+    uy = Jy * inv;
 }
 
 // BGK collision with the Guo source (Eqs. BGKCO, SEDF, GFS, GFSBGK), on the
@@ -354,37 +382,47 @@ __device__ __forceinline__ void velocity(const R d[kQ], R rho, R Fx, R Fy, R &ux
 //   f^eq_i - w_i rho_ref = w_i ((rho - rho_ref) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
 //   S_i                  = (1 - 1/(2 tau)) w_i (3 c.F + 9 (c.F)(c.u) - 3 u.F)
 //   d_i                 <- d_i + (f^eq_i - w_i rho_ref - d_i)/tau + S_i
-// evaluated with the terms of f^eq and S gathered by powers of c_i (below),
-// about eight operations per direction.  Multiply-adds are written as
-// explicit fma(); the file is compiled without implicit contraction, so every
-// inlined copy rounds the same way.
+// Gathered by powers of c_i, omega (f^eq_i - w_i rho_ref) + S_i =
+// w_i [A + c_i.B + (c_i.u)(h c_i.u + m c_i.F)] with
+//   A = omega (rho (1 - 3/2 u.u) - rho_ref) - 3 g u.F,  B = 3 (omega J + g F),
+//   h = 9/2 omega rho,  m = 9 g,  g = 1 - 1/(2 tau),  J = rho u,
+// and d_i <- (1 - omega) d_i + w_i [..].  Opposite directions share all but
+// the sign of c_i.B: T = w (A + (c.u)(h c.u + m c.F)) once per pair, then
+// d_i <- (1 - omega) d_i + T +- w c.B.  The diagonal weight is the axis
+// weight / 4, an exact scaling.  Multiply-adds are written as explicit fma();
+// the file is compiled without implicit contraction, so every inlined copy
+// rounds the same way.
 template <class R>
-__device__ __forceinline__ void collide(R d[kQ], R ref, R rho, R ux, R uy, R Fx, R Fy,
-                                        const Phys<R> &P)
+__device__ __forceinline__ void collide(R d[kQ], R ref, R rho, R ux, R uy, R Jx, R Jy, R Fx,
+                                        R Fy, const Phys<R> &P)
 {
-    // omega (f^eq_i - w_i rho_ref) + S_i = w_i [A + c_i.B + (c_i.u)(h c_i.u + m c_i.F)]
-    // with A = omega (rho (1 - 3/2 u.u) - rho_ref) - 3 g u.F, B = 3 (omega rho u + g F),
-    // h = 9/2 omega rho, m = 9 g (g = 1 - 1/(2 tau)); then d_i <- (1 - omega) d_i + w_i [..].
-    const R om = P.omega, g = P.guo;
-    const R orho = om * rho;
+    const R om = P.omega, g = P.guo, keep = P.keep;
     const R usq = fma(ux, ux, uy * uy);
     const R uF = fma(ux, Fx, uy * Fy);
     const R A = fma(om, fma(rho, R(-1.5) * usq, rho - ref), R(-3) * g * uF);
-    const R Bx = R(3) * fma(orho, ux, g * Fx), By = R(3) * fma(orho, uy, g * Fy);
-    const R h = R(4.5) * orho;
-    const R mx = R(9) * g * Fx, my = R(9) * g * Fy;
-    const R keep = R(1) - om;
-    const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
-    d[0] = fma(keep, d[0], w0 * A);
-    const R cu[8] = {ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
-    const R cm[8] = {mx, my, -mx, -my, mx + my, my - mx, -mx - my, mx - my};
-    const R cB[8] = {Bx, By, -Bx, -By, Bx + By, By - Bx, -Bx - By, Bx - By};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const R w = k < 4 ? w1 : w2;
-        const R q = fma(cu[k], fma(h, cu[k], cm[k]), A + cB[k]);
-        d[k + 1] = fma(keep, d[k + 1], w * q);
-    }
+    d[0] = fma(keep, d[0], R(4.0 / 9.0) * A);
+    // axis directions (w = 1/9): w h = omega rho/2, w m = g, w B = (omega J + g F)/3
+    const R A1 = R(1.0 / 9.0) * A;
+    const R h1 = R(0.5) * om * rho;
+    const R Bx = fma(P.om3, Jx, P.g3 * Fx), By = fma(P.om3, Jy, P.g3 * Fy);
+    const R mx = g * Fx, my = g * Fy;
+    const R Tx = fma(ux, fma(h1, ux, mx), A1);
+    const R Ty = fma(uy, fma(h1, uy, my), A1);
+    d[1] = fma(keep, d[1], Tx + Bx);
+    d[3] = fma(keep, d[3], Tx - Bx);
+    d[2] = fma(keep, d[2], Ty + By);
+    d[4] = fma(keep, d[4], Ty - By);
+    // diagonal directions (w = 1/36): directions 5/7 along (1, 1), 6/8 along (-1, 1)
+    const R A2 = R(0.25) * A1, h2 = R(0.25) * h1;
+    const R u5 = ux + uy, u6 = uy - ux;
+    const R m5 = R(0.25) * (mx + my), m6 = R(0.25) * (my - mx);
+    const R B5 = R(0.25) * (Bx + By), B6 = R(0.25) * (By - Bx);
+    const R T5 = fma(u5, fma(h2, u5, m5), A2);
+    const R T6 = fma(u6, fma(h2, u6, m6), A2);
+    d[5] = fma(keep, d[5], T5 + B5);
+    d[7] = fma(keep, d[7], T5 - B5);
+    d[6] = fma(keep, d[6], T6 + B6);
+    d[8] = fma(keep, d[8], T6 - B6);
 }
 
 // Multiple-relaxation-time collision with the Guo source (Eqs. MRTCO, GFSMRT)
@@ -678,14 +716,14 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
             stencil<DIR, R>(T, C, L, s);
             force<R>(s, P, Fx, Fy);
         }
-        R ux, uy;
-        velocity<R>(f[cur], C.rho, Fx, Fy, ux, uy);
+        R ux, uy, Jx, Jy;
+        velocity<R>(f[cur], C.rho, Fx, Fy, ux, uy, Jx, Jy);
         const size_t row = (size_t)y * c.nx;
         if (MODE == kStep) {
             if constexpr (COLL == LBM_COLL_MRT)
                 collide_mrt<R>(f[cur], C.rho, ux, uy, Fx, Fy, P);
             else
-                collide<R>(f[cur], ref_cur, C.rho, ux, uy, Fx, Fy, P);
+                collide<R>(f[cur], ref_cur, C.rho, ux, uy, Jx, Jy, Fx, Fy, P);
             if (interior) {
                 if constexpr (Store<ST>::local) {
                     // per-cell reference: the new R = sum_i f*_i = ref + s with
@@ -706,8 +744,9 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
                         err += dev - (R)X[i];
                     }
                     store_pops<E>(dst, c, y, cols.o, X);
+                    float *rrow = ref_row(dst, c, y);
                     __builtin_nontemporal_store((float)(ref_cur + (sd + err)),
-                                                (float *)((char *)ref_row(dst, c, y) + 2 * cols.o));
+                                                (float *)((char *)rrow + col_offset(2 * cols.o)));
                 } else {
                     E X[kQ];
 #pragma unroll
@@ -1093,12 +1132,12 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
             R *g = fa[a_cur];
             const R ref_cur = LOC ? ra[(J + 1) % 2] : gref;
             const R rho = rho_a[(J + 1) % 2];
-            R ux, uy;
-            velocity<R>(g, rho, Fx, Fy, ux, uy);
+            R ux, uy, Jx, Jy;
+            velocity<R>(g, rho, Fx, Fy, ux, uy, Jx, Jy);
             if constexpr (COLL == LBM_COLL_MRT)
                 collide_mrt<R>(g, rho, ux, uy, Fx, Fy, P);
             else
-                collide<R>(g, ref_cur, rho, ux, uy, Fx, Fy, P);
+                collide<R>(g, ref_cur, rho, ux, uy, Jx, Jy, Fx, Fy, P);
             // encoded as a single step stores them: rounded to the storage
             // type; per-cell mode: X_i = round(d*_i - w_i s) with s the sum of
             // the d*_i, and the new R = ref + (s + rounding errors)
@@ -1200,12 +1239,12 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
                 force<R>(sv, P, Fx, Fy);
             }
             const R rho = rho_b[(J + 1) % 2];
-            R ux, uy;
-            velocity<R>(g, rho, Fx, Fy, ux, uy);
+            R ux, uy, Jx, Jy;
+            velocity<R>(g, rho, Fx, Fy, ux, uy, Jx, Jy);
             if constexpr (COLL == LBM_COLL_MRT)
                 collide_mrt<R>(g, rho, ux, uy, Fx, Fy, P);
             else
-                collide<R>(g, ref_cur, rho, ux, uy, Fx, Fy, P);
+                collide<R>(g, ref_cur, rho, ux, uy, Jx, Jy, Fx, Fy, P);
             const int sb = m - 6;
             if (interior && sb >= 0 && sb < n) {
                 const int yb = lrow(sb);
@@ -1224,8 +1263,9 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
                         err += dev - (R)X[i];
                     }
                     store_pops<E>(dst, c, yb, cols.o, X);
+                    float *rrow = ref_row(dst, c, yb);
                     __builtin_nontemporal_store((float)(ref_cur + (sd + err)),
-                                                (float *)((char *)ref_row(dst, c, yb) + 2 * cols.o));
+                                                (float *)((char *)rrow + col_offset(2 * cols.o)));
                 } else {
                     E X[kQ];
 #pragma unroll
