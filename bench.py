@@ -77,12 +77,23 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{storage}_2048.j
 DTYPE = {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
          "f16": "f32 arithmetic, f16-shifted storage",
          "f16l": "f32 arithmetic, f16 storage with per-cell f32 reference"}
-# What limits each dominant kernel, from the committed SQ counter profiles
-# (profiles/*_sq_counters.md): wave-cycles waiting to issue, at waits and
-# barriers, and issuing.
+# What limits each dominant kernel, from the committed counter profiles
+# (profiles/sweep2_pass_2048_sq_counters.md, profiles/sweep2_pass_*_2048_traffic.md):
+# counter-measured HBM bytes against a plain device copy, and VALU issue time
+# (SQ_INSTS_VALU x 4 cycles per wave64 instruction over 1024 SIMDs at 2.4 GHz)
+# against the launch time.
 LIMITER = {
-    ("pass2", "f64"): "latency: FP64 dependency chains at two waves per SIMD "
-                      "(profiles/sweep2_pass_f64_2048_sq_counters.md)",
+    ("pass2", "f64"): "hbm: 1.05x the algorithmic bytes at about 4.85 TB/s, within a few percent "
+                      "of a plain device copy; VALU issue 34% of the launch, 41% of wave-cycles "
+                      "waiting on FP64 dependencies at two waves per SIMD "
+                      "(profiles/sweep2_pass_2048_sq_counters.md)",
+    ("pass2", "f32"): "hbm: 1.09x the algorithmic bytes at about 4.8 TB/s, a plain device copy's "
+                      "rate; VALU issue 48% of the launch "
+                      "(profiles/sweep2_pass_2048_sq_counters.md)",
+    ("pass2", "f16"): "valu: FP32 arithmetic issue 78% of the launch; HBM about 2.9 TB/s "
+                      "(profiles/sweep2_pass_2048_sq_counters.md)",
+    ("pass2", "f16l"): "valu: FP32 arithmetic issue 87% of the launch; HBM about 3.1 TB/s "
+                       "(profiles/sweep2_pass_2048_sq_counters.md)",
 }
 
 
@@ -343,7 +354,9 @@ def serve_measure(count, modes=("f32", "f16", "f16l")):
     in each reduced-precision storage mode, against the same jobs run one
     after another on the plain FP64 path (first come, first served).  The
     arrival rate is 0.8 x the capacity: the throughput of the same jobs, cut to
-    2000 steps each, all submitted at once."""
+    2000 steps each, all submitted at once, measured on the second of two such
+    runs (the first one pays the arena's first use and the clocks' ramp from
+    idle, about 15 % of its 0.3 s)."""
     import numpy as np
     import torch
     from paper_2003_07968_amd import lbm
@@ -355,7 +368,8 @@ def serve_measure(count, modes=("f32", "f16", "f16l")):
     quantum = 128
 
     cal = [(p, r, 2000) for p, r, _ in jobs]
-    _, span, st = serve_stream(cal, np.zeros(len(cal)), "f32", arena, quantum)
+    for _ in range(2):
+        _, span, st = serve_stream(cal, np.zeros(len(cal)), "f32", arena, quantum)
     capacity = st["cell_steps"] / span
     rate = 0.8 * capacity / work.mean()
     arrivals = W.poisson_arrivals(len(jobs), rate, seed=7)
@@ -628,7 +642,7 @@ def main():
             "kernel": f"{res['kernel_name']}, {args.storage} storage, {args.collision})",
             "kernel_avg_ms": round(res["launch_ms"], 5),
             "updates_per_launch_per_cell": upl,
-            "limiter": LIMITER.get((kernel, args.storage)),
+            "limiter": LIMITER.get((kernel, args.storage)) if args.collision == "bgk" else None,
             "per_launch_hbm": {
                 "bytes": bpu * N * N,
                 "achieved": round(launch_gbs, 1),
