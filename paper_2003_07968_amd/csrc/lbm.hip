@@ -4,6 +4,7 @@
 // replay, the autotuner and the diagnostics reduction.  The method and the
 // kernels are described in lbm_kernels.hpp; each storage mode's kernels are
 // instantiated in lbm_inst.hip.
+#include "lbm_internal.h"
 #include "lbm_kernels.hpp"
 
 #include <mutex>
@@ -840,14 +841,15 @@ lbm_status lbm_diagnostics_noalloc(lbm_handle *h, double out[6])
     double *s = nullptr;
     e = scratch_on_device(h->device, &s);
     if (e == hipSuccess) e = run_sweep<kDiagnostics>(h, h->cur, nullptr, Fields{}, s);
-    double *red = s + (size_t)kNoAllocTiles * kDiag;
     if (e == hipSuccess) {
+        double *red = s + (size_t)kNoAllocTiles * kDiag;
         hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, h->stream, s,
                            h->tiles.ntiles, red);
         e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out, red, kDiag * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream);
     }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(out, red, kDiag * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     lbm_status st = e == hipSuccess ? read_sticky(h)
                                     : dev_fail(h, e, "diagnostics with the static scratch");
     if (prev != h->device) (void)hipSetDevice(prev);
@@ -1270,3 +1272,22 @@ const char *lbm_last_error(const lbm_handle *h) { return h ? h->last_error.c_str
 void lbm_destroy(lbm_handle *h) { delete h; }
 
 }  // extern "C"
+
+namespace lbm_internal {
+
+lbm_status enqueue_density(lbm_handle *h, double *d_rho)
+{
+    if (!h || !d_rho) return LBM_ERR_INVALID_ARG;
+    Fields fo{d_rho, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipError_t e = run_sweep<kMoments>(h, h->cur, nullptr, fo);
+    return e == hipSuccess ? LBM_OK : dev_fail(h, e, "launching the moments kernel");
+}
+
+lbm_status enqueue_populations(lbm_handle *h, double *d_f)
+{
+    if (!h || !d_f) return LBM_ERR_INVALID_ARG;
+    hipError_t e = run_permute(h, h->cur, d_f, 1);
+    return e == hipSuccess ? LBM_OK : dev_fail(h, e, "copying populations out");
+}
+
+}  // namespace lbm_internal

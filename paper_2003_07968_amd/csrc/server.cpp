@@ -4,8 +4,9 @@
 // memory footprint into a caller-owned arena (first-fit, arena.h), one batch
 // per (storage mode, force switch, collision operator) advanced by the
 // batched step, and retirement with the results copied to the caller's host
-// buffers.  Every device operation goes through the public C ABI of lbm.h
-// plus plain HIP copies on the server's stream.
+// buffers.  Every device operation goes through the public C ABI of lbm.h,
+// two enqueue-only forms of its output calls (lbm_internal.h) and plain HIP
+// copies on the server's stream.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -17,6 +18,7 @@
 
 #include "arena.h"
 #include "lbm.h"
+#include "lbm_internal.h"
 #include "lbm_server.h"
 
 namespace {
@@ -169,17 +171,14 @@ lbm_status step_batches(lbm_server *s)
     return LBM_OK;
 }
 
-// Device -> host copy on the server's stream, complete on return.
-lbm_status copy_out(lbm_server *s, double *h_dst, const double *d_src, size_t bytes)
-{
-    hipError_t e = hipMemcpyAsync(h_dst, d_src, bytes, hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    return e == hipSuccess ? LBM_OK : LBM_ERR_DEVICE;
-}
-
+// Retire the finished jobs.  The stream is drained once, after which every
+// finishing job's sticky error is read; the outputs of those without one
+// (density, populations) are then enqueued with their copies to the caller's
+// host buffers, and the stream is drained once more.  A round that retires
+// many jobs therefore waits twice in all, not once per job and output.
 lbm_status retire(lbm_server *s, int32_t *n_retired)
 {
-    int32_t n = 0;
+    std::vector<Job *> done;
     for (size_t k = 0; k < s->resident.size();) {
         Job *j = s->resident[k];
         if (j->remaining > 0) {
@@ -187,24 +186,46 @@ lbm_status retire(lbm_server *s, int32_t *n_retired)
             continue;
         }
         s->resident.erase(s->resident.begin() + (long)k);
-        lbm_status st = lbm_batch_remove(s->batches[j->key], j->h);
-        if (st == LBM_OK) st = lbm_sync(j->h);
+        done.push_back(j);
+    }
+    if (n_retired) *n_retired = (int32_t)done.size();
+    if (done.empty()) return LBM_OK;
+    bool device_ok = hipStreamSynchronize(s->stream) == hipSuccess;
+    std::vector<lbm_status> st(done.size(), LBM_ERR_DEVICE);
+    bool copies = false;
+    for (size_t k = 0; k < done.size() && device_ok; ++k) {
+        Job *j = done[k];
+        st[k] = lbm_batch_remove(s->batches[j->key], j->h);
+        if (st[k] == LBM_OK) st[k] = lbm_sync(j->h);
+        if (st[k] != LBM_OK) continue;
         double *d_buf = (double *)(s->arena_base + j->buf_off);
         const size_t nc = cells(j->p);
-        if (st == LBM_OK && j->rho_out) {
-            st = lbm_moments(j->h, d_buf, nullptr, nullptr, nullptr, nullptr, nullptr);
-            if (st == LBM_OK) st = copy_out(s, j->rho_out, d_buf, nc * 8);
+        // stream order keeps the density copy ahead of the populations that
+        // reuse the buffer
+        if (j->rho_out) {
+            st[k] = lbm_internal::enqueue_density(j->h, d_buf);
+            if (st[k] == LBM_OK &&
+                hipMemcpyAsync(j->rho_out, d_buf, nc * 8, hipMemcpyDeviceToHost, s->stream) !=
+                    hipSuccess)
+                st[k] = LBM_ERR_DEVICE;
         }
-        if (st == LBM_OK && j->f_out) {
-            st = lbm_get_populations(j->h, d_buf);
-            if (st == LBM_OK) st = copy_out(s, j->f_out, d_buf, 9 * nc * 8);
+        if (st[k] == LBM_OK && j->f_out) {
+            st[k] = lbm_internal::enqueue_populations(j->h, d_buf);
+            if (st[k] == LBM_OK &&
+                hipMemcpyAsync(j->f_out, d_buf, 9 * nc * 8, hipMemcpyDeviceToHost, s->stream) !=
+                    hipSuccess)
+                st[k] = LBM_ERR_DEVICE;
         }
-        finish(s, j, st);
-        ++n;
-        if (st == LBM_ERR_DEVICE) return st;
+        copies = true;
+        if (st[k] == LBM_ERR_DEVICE) device_ok = false;
     }
-    if (n_retired) *n_retired = n;
-    return LBM_OK;
+    if (copies && hipStreamSynchronize(s->stream) != hipSuccess) {
+        device_ok = false;
+        for (lbm_status &x : st)
+            if (x == LBM_OK) x = LBM_ERR_DEVICE;
+    }
+    for (size_t k = 0; k < done.size(); ++k) finish(s, done[k], st[k]);
+    return device_ok ? LBM_OK : LBM_ERR_DEVICE;
 }
 
 // Retire, with their error, the resident jobs whose lattice has left the EOS

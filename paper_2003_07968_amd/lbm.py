@@ -395,6 +395,11 @@ def lbm_destroy(h):
     _load().lbm_destroy(h)
 
 
+def _pinned(shape):
+    """A float64 numpy array in page-locked host memory."""
+    return torch.empty(shape, dtype=torch.float64, pin_memory=True).numpy()
+
+
 # ---- convenience wrapper owning its torch workspace ----
 
 class Lattice:
@@ -553,8 +558,10 @@ class Server:
         params = make_params(p)
         rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
         assert rho0.shape == (params.ny, params.nx)
-        rho = np.empty((params.ny, params.nx)) if want_rho else None
-        f = np.empty((9, params.ny, params.nx)) if want_populations else None
+        # outputs in page-locked host memory, so the server's copies at
+        # retirement are direct DMA; the arrays keep their pinned tensors alive
+        rho = _pinned((params.ny, params.nx)) if want_rho else None
+        f = _pinned((9, params.ny, params.nx)) if want_populations else None
         job = lbm_server_submit(self.handle, params, rho0, nsteps, rho, f)
         self._outputs[job] = (rho, f)
         return job
