@@ -972,10 +972,11 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(
 // r - 1) and 4, 7, 8 from (row r + 1) trade places in the hand-over rings,
 // so populations 4, 7, 8 get the longer rings of 2, 5, 6 (one more LDS row
 // pair, four more registers), and the two rows of the force stencil are
-// picked by direction.  The FP32-arithmetic modes, bound by instruction
-// issue rather than bandwidth, all walk up the lattice: alternating cuts
-// their re-read halo traffic too, but the longer rings cost them more issue
-// time than the traffic saves (2 to 3 % per launch, measured).
+// picked by direction.  The direction is a template argument, one walk
+// instantiated per direction.  The FP32-arithmetic modes all walk up the
+// lattice: alternating cuts their re-read halo traffic too, but they are
+// bound by instruction issue (FP16) or already at a plain copy's bandwidth
+// (FP32), and the longer rings cost them 1 to 1.5 % per launch (measured).
 template <class R, int BX, bool LOC, bool ALT>
 struct Pass2Lds {
     R psi_a[3][BX], psi_b[3][BX];  // psi of A's and B's rows
@@ -992,10 +993,10 @@ struct Pass2Lds {
 template <int ST>
 constexpr bool kAlt2 = ST == LBM_STORE_F64;
 
-template <int BX, int PF, int FORCE, int ST, int COLL>
+template <int BX, int PF, int FORCE, int ST, int COLL, int DIR>
 __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ src,
                                       typename Store<ST>::E *__restrict__ dst, const Coeffs &c,
-                                      long long t, int y0, int dir, int n, int x, const Cols &cols,
+                                      long long t, int y0, int n, int x, const Cols &cols,
                                       bool active, bool valid_b, bool interior,
                                       Pass2Lds<typename Store<ST>::R, BX, Store<ST>::local,
                                                kAlt2<ST>> &L,
@@ -1012,9 +1013,12 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     const R gref = (R)c.rho_ref;
     const int tx = threadIdx.x;
     const int txm = tx > 0 ? tx - 1 : 0, txp = tx < BX - 1 ? tx + 1 : BX - 1;
-    // walk position s is lattice row y0 + dir s (dir = +1, or -1 with ALT)
-    const bool fwd = !ALT || dir > 0;
-    const int ystep = fwd ? 1 : -1;
+    // walk position s is lattice row y0 + DIR s (DIR = +1, or -1 with ALT);
+    // the direction is a template argument, so every choice below that
+    // depends on it is made at compile time
+    static_assert(DIR == 1 || (ALT && DIR == -1), "only the alternating modes walk down");
+    constexpr bool fwd = DIR > 0;
+    constexpr int ystep = DIR;
     auto lrow = [&](int s) {
         const int r = (y0 + ystep * s) % c.ny;
         return r < 0 ? r + c.ny : r;
@@ -1332,10 +1336,13 @@ __device__ __forceinline__ void sweep2_tile(const void *__restrict__ src_v,
     const Cols cols{(uint32_t)x * es, (uint32_t)xm * es, (uint32_t)xp * es};
     unsigned long long bad = ~0ull;
     // odd segments walk down the lattice (FP64 storage; see walk2)
-    const int dir = (kAlt2<ST> && (seg & 1)) ? -1 : 1;
-    const int y0 = dir > 0 ? ys : ye - 1;
-    walk2<BX, PF, FORCE, ST, COLL>((const E *)src_v, (E *)dst_v, c, t, y0, dir, ye - ys, x, cols,
-                                   active, valid_b, interior, lds, bad);
+    if (kAlt2<ST> && (seg & 1))
+        walk2<BX, PF, FORCE, ST, COLL, kAlt2<ST> ? -1 : 1>((const E *)src_v, (E *)dst_v, c, t,
+                                                         ye - 1, ye - ys, x, cols, active,
+                                                         valid_b, interior, lds, bad);
+    else
+        walk2<BX, PF, FORCE, ST, COLL, 1>((const E *)src_v, (E *)dst_v, c, t, ys, ye - ys, x,
+                                          cols, active, valid_b, interior, lds, bad);
     if (bad != ~0ull) atomicMin(err, bad);
 }
 
