@@ -103,21 +103,24 @@ def _oscillation(tau, storage):
     return out
 
 
-# FP64 GPU against the FP64 oracle over 40000 steps (tau = 1.0): extent in
-# lattice units, period relative, densities at the sampled cells normwise.
+# FP64 GPU against the FP64 oracle over 40000 steps, at every tau the oracle
+# run was written for: extent in lattice units, period relative, densities at
+# the sampled cells normwise.
 ORACLE_EXTENT_TOL = 1e-6
 ORACLE_PERIOD_TOL = 1e-6
 ORACLE_RHO_TOL = 1e-9
+ORACLE_TAUS = (0.8, 1.0)
 
 
-def test_oscillation_fp64_matches_oracle_run():
+@pytest.mark.parametrize("tau", ORACLE_TAUS)
+def test_oscillation_fp64_matches_oracle_run(tau):
     require_gpu()
-    gold = _golden(1.0)
-    assert gold is not None, "tests/golden/oscillation_1024_tau1.0.json is missing"
-    g = _oscillation(1.0, "f64")
+    gold = _golden(tau)
+    assert gold is not None, GOLDEN.format(tau=tau) + " is missing"
+    g = _oscillation(tau, "f64")
     e_r = float(np.abs(g["r"] - np.array(gold["extent"])).max())
     e_T = abs(g["T"] / gold["period"] - 1)
-    log(f"tau=1.0 f64 vs oracle: period {g['T']:.3f} / {gold['period']:.3f} (rel {e_T:.1e}), "
+    log(f"tau={tau} f64 vs oracle: period {g['T']:.3f} / {gold['period']:.3f} (rel {e_T:.1e}), "
         f"extent max err {e_r:.2e} cells, drift {g['drift']:.2e} / {gold['drift']:.2e}")
     for t, sn in sorted(g["snaps"].items()):
         o = gold["snapshots"][str(t)]
@@ -148,7 +151,7 @@ DRIFT_TOL = {"f64": 1e-11, "f32": 1e-3, "f16": 5e-2, "f16l": 5e-6}
 @pytest.mark.parametrize("tau", [0.6, 0.8, 1.0])
 def test_oscillation_period_and_mass_drift(tau):
     # the reduced-precision results are taken against the CPU oracle's run
-    # where one was written (tau = 1.0), else against the FP64 GPU path
+    # where one was written (ORACLE_TAUS), else against the FP64 GPU path
     require_gpu()
     ref = _oscillation(tau, "f64")
     gold = _golden(tau)
