@@ -67,6 +67,9 @@ if ROOT not in sys.path:
 # for f16l, the per-cell FP32 reference read and written).
 BYTES_PER_UPDATE = {"f64": 144, "f32": 72, "f16": 36, "f16l": 44}
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
+# wave64 VALU instruction issue: 256 CUs x 4 SIMDs x 2.4 GHz, one FP32 (not
+# packed) or FP64 instruction per 4 cycles per SIMD
+VALU_PEAK_GIPS = 614.4
 METRIC = "MLUPS/GPU and % HBM roofline (FP64 vs FP32/FP16-shifted); p50/p99 time-to-result"
 N = 2048
 TEMPS = (0.6, 0.7, 0.8, 0.9)
@@ -106,9 +109,9 @@ def source_digest():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel, storage):
-    """HBM bytes per launch of `kernel` ("pass2" or "step") from the committed
-    rocprofv3 counter runs, if they were taken on the current kernel source."""
+def counter_record(kernel, storage):
+    """The committed rocprofv3 counter record of `kernel` ("pass2" or "step")
+    in this storage mode, if it was taken on the current kernel source."""
     path = TRAFFIC_FILE.format(kernel=kernel, storage=storage)
     if not os.path.exists(path):
         return None
@@ -116,7 +119,28 @@ def measured_traffic(kernel, storage):
         rec = json.load(fh)
     if rec.get("kernel_source_sha256_16") != source_digest():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def measured_traffic(kernel, storage):
+    """HBM bytes per launch from the committed counter runs, or None."""
+    rec = counter_record(kernel, storage)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def valu_roofline(kernel, storage, launch_ms):
+    """VALU issue of one launch against the chip's issue rate: the launch's
+    wave64 VALU instructions (SQ_INSTS_VALU of the committed counter run; the
+    count is fixed by the code and the launch shape) over its live average
+    duration, against 1024 SIMDs x 2.4 GHz / 4 cycles per wave64 FP32 or FP64
+    instruction = 614.4 G instructions/s.  None without a current record."""
+    rec = counter_record(kernel, storage)
+    if not rec or not rec.get("valu_insts_per_launch"):
+        return None
+    achieved = rec["valu_insts_per_launch"] / (launch_ms / 1e3) / 1e9
+    return {"unit": "G wave64 VALU instructions/s", "achieved": round(achieved, 1),
+            "peak": VALU_PEAK_GIPS, "frac": round(achieved / VALU_PEAK_GIPS, 4),
+            "insts_per_launch": rec["valu_insts_per_launch"]}
 
 
 def copy_calibration():
@@ -549,6 +573,7 @@ def precision_rates(f64_mlups):
                    "kernel_avg_ms": round(r["launch_ms"], 5),
                    "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
                    "per_launch_hbm_frac": round(achieved / upl / HBM_PEAK_GBS, 4),
+                   "valu": valu_roofline(r["kernel"], st, r["launch_ms"]),
                    "limiter": LIMITER.get((r["kernel"], st))}
     return out
 
@@ -643,6 +668,8 @@ def main():
             "kernel_avg_ms": round(res["launch_ms"], 5),
             "updates_per_launch_per_cell": upl,
             "limiter": LIMITER.get((kernel, args.storage)) if args.collision == "bgk" else None,
+            "valu": (valu_roofline(kernel, args.storage, res["launch_ms"])
+                     if args.collision == "bgk" else None),
             "per_launch_hbm": {
                 "bytes": bpu * N * N,
                 "achieved": round(launch_gbs, 1),

@@ -31,3 +31,25 @@ def test_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("step", "f64") is None      # no file
     monkeypatch.setattr(bench, "source_digest", lambda: "fedcba9876543210")
     assert bench.measured_traffic("pass2", "f64") is None     # kernel changed since
+
+
+def test_valu_roofline_from_the_measured_source(tmp_path, monkeypatch):
+    # the VALU issue rate of a launch: instructions per launch from the
+    # counter record, over the live launch time, against 614.4 G/s (1024
+    # SIMDs at 2.4 GHz, one wave64 instruction per 4 cycles)
+    sys.path.insert(0, ROOT)
+    import bench
+    assert abs(bench.VALU_PEAK_GIPS - 256 * 4 * 2.4e9 / 4 / 1e9) < 1e-9
+    rec = {"kernel": "k", "bytes_per_launch": 1, "valu_insts_per_launch": 30720000,
+           "kernel_source_sha256_16": "0123456789abcdef"}
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "traffic_pass2_f16_2048.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE",
+                        str(prof / "traffic_{kernel}_{storage}_2048.json"))
+    monkeypatch.setattr(bench, "source_digest", lambda: "0123456789abcdef")
+    v = bench.valu_roofline("pass2", "f16", 0.1)      # 30.72 M instructions in 100 us
+    assert v["achieved"] == 307.2 and v["frac"] == 0.5 and v["insts_per_launch"] == 30720000
+    assert bench.valu_roofline("pass2", "f32", 0.1) is None    # no file
+    monkeypatch.setattr(bench, "source_digest", lambda: "fedcba9876543210")
+    assert bench.valu_roofline("pass2", "f16", 0.1) is None    # kernel changed since
