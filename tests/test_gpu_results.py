@@ -109,7 +109,7 @@ def _oscillation(tau, storage):
 ORACLE_EXTENT_TOL = 1e-6
 ORACLE_PERIOD_TOL = 1e-6
 ORACLE_RHO_TOL = 1e-9
-ORACLE_TAUS = (0.8, 1.0)
+ORACLE_TAUS = (0.6, 0.8, 1.0)
 
 
 @pytest.mark.parametrize("tau", ORACLE_TAUS)
