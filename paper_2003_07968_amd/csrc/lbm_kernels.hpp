@@ -284,15 +284,44 @@ __device__ __forceinline__ void reconstruct(R d[kQ], const Tri<R> &D, const Tri<
     d[8] = fma(w2, U.l - ref, d[8]);
 }
 
-// Reciprocal and square root in the arithmetic type: IEEE-rounded in FP64 (the
-// reference path); the hardware's single-instruction forms in FP32, whose
-// error of about one ulp is far below the storage rounding of the
-// reduced-precision modes.
-__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+// Reciprocal and quotient in the arithmetic type.  FP64: the hardware
+// reciprocal estimate refined by two Newton steps (x <- x + x (1 - v x), each
+// doubling the correct bits), and the quotient corrected once by its residual
+// (q <- q + (a - b q) / b), within about one ulp of the rounded result and
+// with a shorter dependent chain than the IEEE division sequence; the
+// arguments are well scaled (rho and (1 - b rho)^3 inside the EOS domain).
+// FP32: the hardware's single-instruction forms, whose error of about one ulp
+// is far below the storage rounding of the reduced-precision modes.
+__device__ __forceinline__ double recip(double v)
+{
+    double x = __builtin_amdgcn_rcp(v);
+    x = fma(x, fma(-v, x, 1.0), x);
+    return fma(x, fma(-v, x, 1.0), x);
+}
 __device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
-__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+__device__ __forceinline__ double quot(double a, double b)
+{
+    const double x = recip(b);
+    const double q = a * x;
+    return fma(fma(-b, q, a), x, q);
+}
 __device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double root(double v) { return sqrt(v); }
+// Square root: FP64 from the hardware reciprocal-square-root estimate y,
+// g = v y and h = y/2 refined together (r = 1/2 - g h; g += g r; h += h r),
+// then g corrected twice by its residual (g += (v - g g) h), within about one
+// ulp; v >= 0 here (the EOS domain check), and v = 0 gives 0.  FP32: the
+// single-instruction form.
+__device__ __forceinline__ double root(double v)
+{
+    const double y = __builtin_amdgcn_rsq(v);
+    double g = v * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    g = fma(fma(-g, g, v), h, g);
+    g = fma(fma(-g, g, v), h, g);
+    return v > 0.0 ? g : v;
+}
 __device__ __forceinline__ float root(float v) { return __builtin_amdgcn_sqrtf(v); }
 
 // Density (Eq. FD) and pseudopotential (Eqs. CSEOS, DED) from the stored
