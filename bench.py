@@ -70,6 +70,8 @@ HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 # wave64 VALU instruction issue: 256 CUs x 4 SIMDs x 2.4 GHz, one FP32 (not
 # packed) or FP64 instruction per 4 cycles per SIMD
 VALU_PEAK_GIPS = 614.4
+# storage modes whose two-step pass is bound by VALU issue (committed counters)
+ISSUE_BOUND = ("f16", "f16l")
 METRIC = "MLUPS/GPU and % HBM roofline (FP64 vs FP32/FP16-shifted); p50/p99 time-to-result"
 N = 2048
 TEMPS = (0.6, 0.7, 0.8, 0.9)
@@ -679,6 +681,14 @@ def main():
             },
         },
     }
+    # the issue-bound modes (FP16 storage, FP32 arithmetic) are priced against
+    # the VALU issue rate, the HBM figures kept beside it
+    rf = out["roofline"]
+    if args.storage in ISSUE_BOUND and rf["valu"] is not None:
+        v = rf.pop("valu")
+        rf["hbm"] = {k: rf[k] for k in ("achieved", "peak", "unit", "frac")}
+        rf.update(bound="alu", achieved=v["achieved"], peak=v["peak"], unit=v["unit"],
+                  frac=v["frac"], valu_insts_per_launch=v["insts_per_launch"])
     if res["block_rates"]:
         import numpy as np
         br = res["block_rates"]
