@@ -97,7 +97,7 @@ LIMITER = {
                       "(profiles/sweep2_pass_2048_sq_counters.md)",
     ("pass2", "f16"): "valu: FP32 arithmetic issue 77% of the launch; HBM about 2.9 TB/s "
                       "(profiles/sweep2_pass_2048_sq_counters.md)",
-    ("pass2", "f16l"): "valu: FP32 arithmetic issue 85% of the launch; HBM about 3.1 TB/s "
+    ("pass2", "f16l"): "valu: FP32 arithmetic issue 84% of the launch; HBM about 3.1 TB/s "
                        "(profiles/sweep2_pass_2048_sq_counters.md)",
 }
 

@@ -328,10 +328,19 @@ __device__ __forceinline__ float root(float v) { return __builtin_amdgcn_sqrtf(v
 // deviations d_i = f_i - w_i rho_ref: rho = rho_ref + sum_i d_i.  Returns
 // false when the density is outside the EOS domain (with FORCE = 0, when it
 // is not positive and finite).
+// FP64 arithmetic goes with FP64 storage, which keeps the populations
+// themselves (reference density 0): the reference terms are left out there.
+template <class R>
+constexpr bool kNoRef = std::is_same_v<R, double>;
+
 template <class R>
 __device__ __forceinline__ R density(const R d[kQ], R ref)
 {
-    return ((((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8]) + ref;
+    const R s = (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8];
+    if constexpr (kNoRef<R>)
+        return s;
+    else
+        return s + ref;
 }
 
 template <int FORCE, class R>
@@ -428,7 +437,7 @@ __device__ __forceinline__ void collide(R d[kQ], R ref, R rho, R ux, R uy, R Jx,
     const R om = P.omega, g = P.guo, keep = P.keep;
     const R usq = fma(ux, ux, uy * uy);
     const R uF = fma(ux, Fx, uy * Fy);
-    const R A = fma(om, fma(rho, R(-1.5) * usq, rho - ref), R(-3) * g * uF);
+    const R A = fma(om, fma(rho, R(-1.5) * usq, kNoRef<R> ? rho : rho - ref), R(-3) * g * uF);
     d[0] = fma(keep, d[0], R(4.0 / 9.0) * A);
     // axis directions (w = 1/9): w h = omega rho/2, w m = g, w B = (omega J + g F)/3
     const R A1 = R(1.0 / 9.0) * A;
