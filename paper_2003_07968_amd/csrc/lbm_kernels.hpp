@@ -1027,6 +1027,9 @@ struct Pass2Lds {
     float r_in[LOC ? 2 : 1][BX], r_out[LOC ? 4 : 1][BX];
 };
 
+// Halo columns of the two-step pass on each side of its output strip.
+constexpr int kHalo2 = 3;
+
 // Segments that alternate their walk direction (see walk2).
 template <int ST>
 constexpr bool kAlt2 = ST == LBM_STORE_F64;
@@ -1049,8 +1052,14 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     constexpr int K = PF + 2;
     const Phys<R> P(c);
     const R gref = (R)c.rho_ref;
+    // Lanes hold the tile's columns as a ring (see sweep2_tile): lane l holds
+    // column position (l + kHalo2) mod BX, so the output columns start at
+    // lane 0 and every wave stores whole cache lines.  Neighbour lanes are
+    // taken modulo BX; the two ends of the ring are the outermost halo
+    // columns, whose results no output uses.
+    static_assert((BX & (BX - 1)) == 0, "ring of lanes needs a power-of-two width");
     const int tx = threadIdx.x;
-    const int txm = tx > 0 ? tx - 1 : 0, txp = tx < BX - 1 ? tx + 1 : BX - 1;
+    const int txm = (tx + BX - 1) & (BX - 1), txp = (tx + 1) & (BX - 1);
     // walk position s is lattice row y0 + DIR s (DIR = +1, or -1 with ALT);
     // the direction is a template argument, so every choice below that
     // depends on it is made at compile time
@@ -1083,10 +1092,10 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     Tri<R> ta[3];
     R ra[2];
     RefPair<R> rl[2];
-    const bool first = tx == 0;
+    const bool first = tx == BX - kHalo2;  // column position 0, the leftmost
     // R at x - 1, x, x + 1 from a lane's own and side values and an LDS row
     auto tri_from = [&](const RefPair<R> &v, const float *buf) {
-        return first ? Tri<R>{v.side, v.own, (R)buf[1]} : Tri<R>{(R)buf[txm], v.own, v.side};
+        return first ? Tri<R>{v.side, v.own, (R)buf[txp]} : Tri<R>{(R)buf[txm], v.own, v.side};
     };
     auto tri_lds = [&](const float *buf) {
         return Tri<R>{(R)buf[txm], (R)buf[tx], (R)buf[txp]};
@@ -1334,8 +1343,6 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     }, std::make_integer_sequence<int, U - 1>{});
 }
 
-// Halo columns of the two-step pass on each side of its output strip.
-constexpr int kHalo2 = 3;
 
 // Waves per SIMD the two-step pass is compiled for.  FP64 runs at two (172
 // VGPRs with BGK).  Three fit without spills when the density is recomputed
@@ -1362,12 +1369,16 @@ __device__ __forceinline__ void sweep2_tile(const void *__restrict__ src_v,
     const int xe = min(c.nx, xs + tl.width);
     const int ys = (int)((long long)seg * c.ny / tl.nseg);
     const int ye = (int)((long long)(seg + 1) * c.ny / tl.nseg);
-    const int tx = threadIdx.x;
+    // lane tx holds column xs - kHalo2 + pos: the output columns xs .. xe - 1
+    // in lanes 0 .. width - 1 (so that each wave's stores start on a cache
+    // line of an aligned strip), the right halo after them and the left halo
+    // in the last kHalo2 lanes
+    const int pos = (threadIdx.x + kHalo2) & (BX - 1);
     const int width = xe - xs;  // output columns, <= BX - 2 kHalo2
-    const bool active = tx < width + 2 * kHalo2;
-    const bool valid_b = tx >= kHalo2 - 1 && tx <= width + kHalo2;
-    const bool interior = tx >= kHalo2 && tx < width + kHalo2;
-    int x = (xs - kHalo2 + (active ? tx : kHalo2)) % c.nx;
+    const bool active = pos < width + 2 * kHalo2;
+    const bool valid_b = pos >= kHalo2 - 1 && pos <= width + kHalo2;
+    const bool interior = pos >= kHalo2 && pos < width + kHalo2;
+    int x = (xs - kHalo2 + (active ? pos : kHalo2)) % c.nx;
     x = x < 0 ? x + c.nx : x;
     const int xm = wrap_lo(x - 1, c.nx), xp = wrap_hi(x + 1, c.nx);
     constexpr uint32_t es = sizeof(E);
