@@ -641,8 +641,11 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
     constexpr bool LOC = Store<ST>::local;
     constexpr int K = PF + 2;
     const Phys<R> P(c);
+    // lanes hold the tile's columns as a ring (see sweep_tile); neighbour
+    // lanes are taken modulo BX, the two ends of the ring being the halo
+    // columns, whose own results are not stored
     const int tx = threadIdx.x;
-    const int txm = tx > 0 ? tx - 1 : 0, txp = tx < BX - 1 ? tx + 1 : BX - 1;
+    const int txm = tx == 0 ? BX - 1 : tx - 1, txp = tx == BX - 1 ? 0 : tx + 1;
     const int nrows = ye - ys;
     const int y0 = DIR > 0 ? ys : ye - 1;
     // wrapped lattice row of segment row k (k in [-1, nrows])
@@ -660,14 +663,14 @@ __device__ __forceinline__ void walk(const typename Store<ST>::E *__restrict__ s
     RefPair<R> rl[K];
     Tri<R> tr[K];
     const R gref = (R)c.rho_ref;  // the shifted modes' reference density
-    const bool first = tx == 0;
+    const bool first = tx == BX - 1;  // column position 0, the left halo
     // the left neighbour of every lane but the first comes from the lane on
     // its left; the right neighbour was loaded (the first lane takes it from
-    // lane 1)
+    // the lane on its right)
     auto tri_of = [&](const RefPair<R> &v, float *buf) {
         buf[tx] = (float)v.own;
         __syncthreads();
-        return first ? Tri<R>{v.side, v.own, (R)buf[1]} : Tri<R>{(R)buf[txm], v.own, v.side};
+        return first ? Tri<R>{v.side, v.own, (R)buf[txp]} : Tri<R>{(R)buf[txm], v.own, v.side};
     };
     // lattice rows r - 1 and r + 1 of segment row k are segment rows k - DIR and k + DIR
     auto rebuild = [&](R d[kQ], const Tri<R> &prev, const Tri<R> &here, const Tri<R> &next) {
@@ -849,11 +852,14 @@ __device__ __forceinline__ void sweep_tile(const void *__restrict__ src_v, void 
     const int ys = (int)((long long)seg * c.ny / tl.nseg);
     const int ye = (int)((long long)(seg + 1) * c.ny / tl.nseg);
 
-    const int tx = threadIdx.x;
+    // lane tx holds column xs - 1 + pos: the interior columns in lanes
+    // 0 .. width - 1 (each wave's stores start on a cache line of the aligned
+    // strip), the right halo after them and the left halo in the last lane
+    const int pos = (int)((threadIdx.x + 1) % BX);
     const int width = xe - xs;                 // interior columns, <= BX - 2
-    const bool active = tx <= width + 1;
-    const bool interior = tx >= 1 && tx <= width;
-    int x = xs - 1 + (active ? tx : 1);
+    const bool active = pos <= width + 1;
+    const bool interior = pos >= 1 && pos <= width;
+    int x = xs - 1 + (active ? pos : 1);
     x = wrap_hi(wrap_lo(x, c.nx), c.nx);
     const int xm = wrap_lo(x - 1, c.nx), xp = wrap_hi(x + 1, c.nx);
     constexpr uint32_t es = sizeof(E);
@@ -876,7 +882,7 @@ __device__ __forceinline__ void sweep_tile(const void *__restrict__ src_v, void 
         for (int j = 0; j < kDiag - 1; ++j)
             out[j] = warp_or_block_sum<BX>(acc[j], red);
         out[kDiag - 1] = warp_or_block_max<BX>(acc[kDiag - 1], red);
-        if (tx == 0) {
+        if (threadIdx.x == 0) {
 #pragma unroll
             for (int j = 0; j < kDiag; ++j)
                 partials[(size_t)tile * kDiag + j] = out[j];
