@@ -88,12 +88,12 @@ DTYPE = {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
 # (SQ_INSTS_VALU x 4 cycles per wave64 instruction over 1024 SIMDs at 2.4 GHz)
 # against the launch time.
 LIMITER = {
-    ("pass2", "f64"): "hbm and latency: 1.05x the algorithmic bytes at about 4.9 TB/s, a plain "
-                      "device copy's rate but 78% of the best same-pattern stream probe; VALU "
-                      "issue 30% of the launch, 42% of wave-cycles waiting on FP64 dependencies "
+    ("pass2", "f64"): "hbm and latency: 1.03x the algorithmic bytes at about 5.0 TB/s, a plain "
+                      "device copy's rate but 80% of the best same-pattern stream probe; VALU "
+                      "issue 31% of the launch, 39% of wave-cycles waiting on FP64 dependencies "
                       "at two waves per SIMD (profiles/sweep2_pass_2048_sq_counters.md)",
-    ("pass2", "f32"): "hbm: 1.09x the algorithmic bytes at about 4.8 TB/s, a plain device copy's "
-                      "rate; VALU issue 48% of the launch "
+    ("pass2", "f32"): "hbm: 1.09x the algorithmic bytes at about 4.7 TB/s, a plain device copy's "
+                      "rate; VALU issue 47% of the launch "
                       "(profiles/sweep2_pass_2048_sq_counters.md)",
     ("pass2", "f16"): "valu: FP32 arithmetic issue 77% of the launch; HBM about 2.9 TB/s "
                       "(profiles/sweep2_pass_2048_sq_counters.md)",
