@@ -92,8 +92,8 @@ LIMITER = {
                       "device copy's rate but 80% of the best same-pattern stream probe; VALU "
                       "issue 31% of the launch, 39% of wave-cycles waiting on FP64 dependencies "
                       "at two waves per SIMD (profiles/sweep2_pass_2048_sq_counters.md)",
-    ("pass2", "f32"): "hbm: 1.09x the algorithmic bytes at about 4.7 TB/s, a plain device copy's "
-                      "rate; VALU issue 47% of the launch "
+    ("pass2", "f32"): "hbm: 1.02x the algorithmic bytes at about 4.4 TB/s, near a plain device "
+                      "copy's rate; VALU issue 48% of the launch "
                       "(profiles/sweep2_pass_2048_sq_counters.md)",
     ("pass2", "f16"): "valu: FP32 arithmetic issue 77% of the launch; HBM about 2.9 TB/s "
                       "(profiles/sweep2_pass_2048_sq_counters.md)",

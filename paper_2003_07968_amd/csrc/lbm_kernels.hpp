@@ -1008,19 +1008,18 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(
 // from the own lane and stay in registers.  Register sets rotate with period 6
 // (the loop is unrolled six times).
 //
-// Walk direction (FP64 storage, ALT): neighbouring segments walk in opposite
-// directions, as in the single-step sweep, so that the six rows two segments
-// share (three halo rows of each) are read by both near the same time, at
-// the start or at the end of both walks, and the second read comes from L2.
-// Walking down the lattice, the rows B pulls populations 2, 5, 6 from (row
-// r - 1) and 4, 7, 8 from (row r + 1) trade places in the hand-over rings,
-// so populations 4, 7, 8 get the longer rings of 2, 5, 6 (one more LDS row
-// pair, four more registers), and the two rows of the force stencil are
-// picked by direction.  The direction is a template argument, one walk
-// instantiated per direction.  The FP32-arithmetic modes all walk up the
-// lattice: alternating cuts their re-read halo traffic too, but they are
-// bound by instruction issue (FP16) or already at a plain copy's bandwidth
-// (FP32), and the longer rings cost them 1 to 1.5 % per launch (measured).
+// Walk direction (FP64 and FP32 storage, ALT): neighbouring segments walk
+// in opposite directions, as in the single-step sweep, so that the six rows
+// two segments share (three halo rows of each) are read by both near the
+// same time, at the start or at the end of both walks, and the second read
+// comes from L2.  Walking down the lattice, the rows B pulls populations
+// 2, 5, 6 from (row r - 1) and 4, 7, 8 from (row r + 1) trade places in the
+// hand-over rings, so populations 4, 7, 8 get the longer rings of 2, 5, 6
+// (one more LDS row pair, two or four more registers), and the two rows of
+// the force stencil are picked by direction.  The direction is a template
+// argument, one walk instantiated per direction.  The FP16 modes walk up the
+// lattice: they are bound by instruction issue, and the longer rings cost
+// them more (1.6 % per launch, measured) than the saved re-reads gain.
 template <class R, int BX, bool LOC, bool ALT>
 struct Pass2Lds {
     R psi_a[3][BX], psi_b[3][BX];  // psi of A's and B's rows
@@ -1038,7 +1037,7 @@ constexpr int kHalo2 = 3;
 
 // Segments that alternate their walk direction (see walk2).
 template <int ST>
-constexpr bool kAlt2 = ST == LBM_STORE_F64;
+constexpr bool kAlt2 = ST == LBM_STORE_F64 || ST == LBM_STORE_F32_SHIFTED;
 
 template <int BX, int PF, int FORCE, int ST, int COLL, int DIR>
 __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ src,
@@ -1390,7 +1389,7 @@ __device__ __forceinline__ void sweep2_tile(const void *__restrict__ src_v,
     constexpr uint32_t es = sizeof(E);
     const Cols cols{(uint32_t)x * es, (uint32_t)xm * es, (uint32_t)xp * es};
     unsigned long long bad = ~0ull;
-    // odd segments walk down the lattice (FP64 storage; see walk2)
+    // odd segments walk down the lattice (FP64 and FP32 storage; see walk2)
     if (kAlt2<ST> && (seg & 1))
         walk2<BX, PF, FORCE, ST, COLL, kAlt2<ST> ? -1 : 1>((const E *)src_v, (E *)dst_v, c, t,
                                                          ye - 1, ye - ys, x, cols, active,
