@@ -44,7 +44,7 @@ def test_strip_parity_with_oracle_over_20000_steps(oracle):
     # operation), and this slab amplifies perturbations: a random one-ulp
     # change of the oracle's own initial density grows to 1.8e-14 in 2000
     # steps and 7e-14 in 5000.  Rounding differences made at every step add up
-    # to 4e-13 at t = 2000 and about 6e-12 at t = 20000 (measured), so the
+    # to 7e-13 at t = 2000 and about 8e-12 at t = 20000 (measured), so the
     # 1e-12 bar holds over the first few thousand steps only.
     require_gpu()
     p, rho0 = W.slab_case(n=N, ny=8, tr=0.8)

@@ -137,12 +137,12 @@ def test_oscillation_fp64_matches_oracle_run(tau):
 # Tolerances of the reduced-precision results against FP64 (period: relative;
 # extent: lattice units, max over the time series; drift: |dM|/M at 40000
 # steps), a few times the measured worst case over tau in {0.6, 0.8, 1.0}:
-#   FP32: period 3.8e-4, extent 0.041 cells, drift 2.2e-4 (tau = 0.6);
-#   FP16 with one global reference: drift 2.3e-2 (period and extent not
+#   FP32: period 7.6e-4 (tau = 0.6), extent 0.056 cells, drift 5.6e-5;
+#   FP16 with one global reference: drift 1.7e-2 (period and extent not
 #   asserted, see above);
 #   FP16 with a per-cell FP32 reference (f16l): period 1.2e-2 (tau = 1),
-#   extent 0.66 cells, drift 4.2e-7;
-#   FP64: drift 2.9e-12 (mass is conserved to rounding).
+#   extent 0.64 cells, drift 4.2e-7;
+#   FP64: drift 3.9e-12 (mass is conserved to rounding).
 PERIOD_TOL = {"f32": 2e-3, "f16l": 4e-2}
 EXTENT_TOL = {"f32": 0.2, "f16l": 2.0}
 DRIFT_TOL = {"f64": 1e-11, "f32": 1e-3, "f16": 5e-2, "f16l": 5e-6}
@@ -178,8 +178,8 @@ def test_oscillation_period_and_mass_drift(tau):
 
 
 LAPLACE_RADII = (16.0, 22.0, 28.0, 34.0)
-# relative errors against FP64; measured: FP32 1.4e-4 per radius and 1.3e-5 on
-# the fitted slope, FP16 0.13 and 0.084, f16l 7.6e-4 and 1.4e-3 (the FP16
+# relative errors against FP64; measured: FP32 1.5e-4 per radius and 2.0e-5 on
+# the fitted slope, FP16 0.16 and 0.15, f16l 9.9e-4 and 7.5e-4 (the FP16
 # figures follow the last bit of the FP32 arithmetic: the global-reference
 # format loses collision increments below half an ulp of its deviations)
 DP_TOL = {"f32": 1e-3, "f16": 0.3, "f16l": 5e-3}

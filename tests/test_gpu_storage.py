@@ -27,7 +27,7 @@ pytestmark = pytest.mark.gpu
 # flipped binary16 rounding of a deviation is 2^-11 of its size.
 # f16l (binary16 deviations from a per-cell FP32 reference): a flipped
 # rounding is 2^-11 of a deviation that is at most ~1e-2 of f (at interfaces),
-# some 35 times less than with the global reference; measured 9.5e-5 after
+# some 35 times less than with the global reference; measured 8.8e-5 after
 # 100 steps of the MRT droplet.
 EMULATED_TOL = {"f32": 2e-5, "f16": 2e-3, "f16l": 5e-4}
 
@@ -90,7 +90,7 @@ def test_launch_shapes_bitwise_identical(storage, collision):
 # lost, and not symmetrically, so the mass drifts by about 1 % per 2000
 # steps on this two-phase slab (the FP64-arithmetic oracle with the same
 # storage rounding drifts alike).  The coexistence densities stay close.
-# f16l (per-cell FP32 reference) measured: drift 1.2e-7, liquid 1.7e-5, gas 1.1e-4.
+# f16l (per-cell FP32 reference) measured: drift 1.3e-7, liquid 6.0e-6, gas 4.5e-5.
 MASS_DRIFT_TOL = {"f32": 1e-5, "f16": 3e-2, "f16l": 1e-6}   # |dM|/M after 2000 steps
 COEX_TOL = {"f32": (1e-5, 5e-5), "f16": (2e-3, 1e-2),       # (liquid, gas) relative,
             "f16l": (1e-4, 5e-4)}                           # 8000 steps
