@@ -90,15 +90,16 @@ DTYPE = {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
 LIMITER = {
     ("pass2", "f64"): "hbm and latency: 1.03x the algorithmic bytes at about 5.0 TB/s, a plain "
                       "device copy's rate but 80% of the best same-pattern stream probe; VALU "
-                      "issue 31% of the launch, 39% of wave-cycles waiting on FP64 dependencies "
-                      "at two waves per SIMD (profiles/sweep2_pass_2048_sq_counters.md)",
+                      "issue 31% of the launch, 40% of wave-cycles waiting on FP64 dependencies "
+                      "at two waves per SIMD; a third wave per SIMD measured no faster "
+                      "(profiles/sweep2_pass_2048_sq_counters.md)",
     ("pass2", "f32"): "hbm: 1.02x the algorithmic bytes at about 4.4 TB/s, near a plain device "
                       "copy's rate; VALU issue 48% of the launch "
                       "(profiles/sweep2_pass_2048_sq_counters.md)",
-    ("pass2", "f16"): "valu: FP32 arithmetic issue 77% of the launch; HBM about 2.9 TB/s "
-                      "(profiles/sweep2_pass_2048_sq_counters.md)",
-    ("pass2", "f16l"): "valu: FP32 arithmetic issue 84% of the launch; HBM about 3.1 TB/s "
-                       "(profiles/sweep2_pass_2048_sq_counters.md)",
+    ("pass2", "f16"): "valu: FP32 arithmetic issue 77% of the launch; HBM about 3.0 TB/s, 1.05x "
+                      "the algorithmic bytes (profiles/sweep2_pass_2048_sq_counters.md)",
+    ("pass2", "f16l"): "valu: FP32 arithmetic issue 84% of the launch; HBM about 2.8 TB/s, 1.06x "
+                       "the algorithmic bytes (profiles/sweep2_pass_2048_sq_counters.md)",
 }
 
 

@@ -8,6 +8,7 @@
 #include "lbm_kernels.hpp"
 
 #include <mutex>
+#include <vector>
 
 using namespace lbmk;
 
@@ -559,6 +560,38 @@ double time_launches(hipStream_t stream, int reps, Fn &&fn)
     return us;
 }
 
+// A launch shape and its timed duration per launch.
+struct Shape {
+    double us;
+    int bx, rows;
+};
+
+// Second pass of a tuner: the kRefine fastest shapes of the first pass (one
+// sample of three launches each) timed again as the best of three samples of
+// ten launches, so that a shape wins by being faster and not by one lucky
+// sample.  set(shape) puts a shape in place (false: it does not fit), fn()
+// makes one launch.  Returns the fastest shape; us < 0 if a launch failed,
+// or 1e300 with no candidates.
+constexpr int kRefine = 3;
+template <class Set, class Fn>
+Shape refine_shapes(hipStream_t stream, std::vector<Shape> cands, Set &&set, Fn &&fn)
+{
+    std::sort(cands.begin(), cands.end(),
+              [](const Shape &a, const Shape &b) { return a.us < b.us; });
+    Shape best{1e300, 0, 0};
+    for (size_t i = 0; i < cands.size() && i < (size_t)kRefine; ++i) {
+        if (!set(cands[i])) continue;
+        double t = 1e300;
+        for (int k = 0; k < 3; ++k) {
+            const double us = time_launches(stream, 10, fn);
+            if (us < 0) return Shape{-1.0, cands[i].bx, cands[i].rows};
+            t = std::min(t, us);
+        }
+        if (t < best.us) best = Shape{t, cands[i].bx, cands[i].rows};
+    }
+    return best;
+}
+
 const int kTuneWidths[] = {64, 128, 192, 256, 320, 384, 512};
 const int kTuneRows[] = {3, 5, 7, 9, 13, 17};
 const int kTuneWidths2[] = {128, 256, 512};
@@ -953,29 +986,37 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3])
     {
         const int bx0 = h->bx, rows0 = h->seg_rows;
         const Tiles tl0 = h->tiles;
+        auto set = [&](const Shape &sh) {
+            Tiles tl;
+            if (!make_tiles(h->p.nx, h->p.ny, sh.bx, sh.rows, align, &tl)) return false;
+            h->bx = sh.bx;
+            h->seg_rows = sh.rows;
+            h->tiles = tl;
+            return true;
+        };
+        auto launch = [&] { return run_sweep<kStep>(h, h->cur, h->nxt, Fields{}); };
+        auto fail = [&] {
+            h->bx = bx0;
+            h->seg_rows = rows0;
+            h->tiles = tl0;
+            return dev_fail(h, hipGetLastError(), "timing a launch shape");
+        };
+        std::vector<Shape> cands;
         for (int bx : kTuneWidths)
             for (int rows : kTuneRows) {
-                Tiles tl;
-                if (!make_tiles(h->p.nx, h->p.ny, bx, std::min(rows, h->p.ny), align, &tl))
-                    continue;
-                h->bx = bx;
-                h->seg_rows = std::min(rows, h->p.ny);
-                h->tiles = tl;
-                const double us = time_launches(h->stream, 3, [&] {
-                    return run_sweep<kStep>(h, h->cur, h->nxt, Fields{});
-                });
-                if (us < 0) {
-                    h->bx = bx0;
-                    h->seg_rows = rows0;
-                    h->tiles = tl0;
-                    return dev_fail(h, hipGetLastError(), "timing a launch shape");
-                }
-                if (us < best1) {
-                    best1 = us;
-                    bx1 = bx;
-                    rows1 = h->seg_rows;
-                }
+                const Shape sh{0.0, bx, std::min(rows, h->p.ny)};
+                if (!set(sh)) continue;
+                const double us = time_launches(h->stream, 3, launch);
+                if (us < 0) return fail();
+                cands.push_back(Shape{us, sh.bx, sh.rows});
             }
+        const Shape b = refine_shapes(h->stream, cands, set, launch);
+        if (b.us < 0) return fail();
+        if (b.us < 1e300) {
+            best1 = b.us;
+            bx1 = b.bx;
+            rows1 = b.rows;
+        }
         make_tiles(h->p.nx, h->p.ny, bx1, rows1, align, &h->tiles);
         h->bx = bx1;
         h->seg_rows = rows1;
@@ -986,6 +1027,23 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3])
     if (h->fuse == 2) {
         const Tiles tl0 = h->tiles2;
         const int bx0 = h->bx2, rows0 = h->seg_rows2;
+        auto set = [&](const Shape &sh) {
+            Tiles tl;
+            if (!make_tiles2(h->p.nx, h->p.ny, sh.bx, sh.rows, strip_align2(h->p.storage), &tl))
+                return false;
+            h->bx2 = sh.bx;
+            h->seg_rows2 = sh.rows;
+            h->tiles2 = tl;
+            return true;
+        };
+        auto launch = [&] { return run_sweep2(h, h->cur, h->nxt); };
+        auto fail = [&] {
+            h->bx2 = bx0;
+            h->seg_rows2 = rows0;
+            h->tiles2 = tl0;
+            return dev_fail(h, hipGetLastError(), "timing a launch shape");
+        };
+        std::vector<Shape> cands;
         for (int bx : kTuneWidths2)
             for (int k = -1; k < (int)(sizeof(kTuneRows2) / sizeof(int)); ++k) {
                 // k = -1: the default segment length for this width
@@ -996,26 +1054,20 @@ lbm_status lbm_autotune(lbm_handle *h, double out[3])
                         continue;
                 } else {
                     r = std::min(kTuneRows2[k], h->p.ny);
-                    if (!make_tiles2(h->p.nx, h->p.ny, bx, r, strip_align2(h->p.storage), &tl))
-                        continue;
                 }
-                h->bx2 = bx;
-                h->seg_rows2 = r;
-                h->tiles2 = tl;
-                const double us = time_launches(
-                    h->stream, 3, [&] { return run_sweep2(h, h->cur, h->nxt); });
-                if (us < 0) {
-                    h->bx2 = bx0;
-                    h->seg_rows2 = rows0;
-                    h->tiles2 = tl0;
-                    return dev_fail(h, hipGetLastError(), "timing a launch shape");
-                }
-                if (0.5 * us < best2) {
-                    best2 = 0.5 * us;
-                    bx2 = bx;
-                    rows2 = r;
-                }
+                const Shape sh{0.0, bx, r};
+                if (!set(sh)) continue;
+                const double us = time_launches(h->stream, 3, launch);
+                if (us < 0) return fail();
+                cands.push_back(Shape{us, bx, r});
             }
+        const Shape b = refine_shapes(h->stream, cands, set, launch);
+        if (b.us < 0) return fail();
+        if (b.us < 1e300) {
+            best2 = 0.5 * b.us;
+            bx2 = b.bx;
+            rows2 = b.rows;
+        }
         make_tiles2(h->p.nx, h->p.ny, bx2, rows2, strip_align2(h->p.storage), &h->tiles2);
         h->bx2 = bx2;
         h->seg_rows2 = rows2;
@@ -1181,20 +1233,28 @@ lbm_status lbm_batch_autotune(lbm_batch *b, double out[3])
     b->fuse_max = 1;
     double best1 = 1e300;
     int bx1 = b->bx, rows1 = b->rows;
-    for (int bx : kTuneWidths)
-        for (int rows : kTuneRows) {
-            b->bx = bx;
-            b->rows = rows;
-            if (batch_upload(b) != LBM_OK) continue;
-            const double us =
-                time_launches(b->stream, 3,
-                              [&] { return batch_launch_steps(b, 1, nullptr, 0, 0); });
-            if (us >= 0 && us < best1) {
-                best1 = us;
-                bx1 = bx;
-                rows1 = rows;
+    {
+        auto set = [&](const Shape &sh) {
+            b->bx = sh.bx;
+            b->rows = sh.rows;
+            return batch_upload(b) == LBM_OK;
+        };
+        auto launch = [&] { return batch_launch_steps(b, 1, nullptr, 0, 0); };
+        std::vector<Shape> cands;
+        for (int bx : kTuneWidths)
+            for (int rows : kTuneRows) {
+                const Shape sh{0.0, bx, rows};
+                if (!set(sh)) continue;
+                const double us = time_launches(b->stream, 3, launch);
+                if (us >= 0) cands.push_back(Shape{us, bx, rows});
             }
+        const Shape best = refine_shapes(b->stream, cands, set, launch);
+        if (best.us >= 0 && best.us < 1e300) {
+            best1 = best.us;
+            bx1 = best.bx;
+            rows1 = best.rows;
         }
+    }
     b->bx = bx1;
     b->rows = rows1;
     double best2 = 1e300;
@@ -1202,20 +1262,26 @@ lbm_status lbm_batch_autotune(lbm_batch *b, double out[3])
     if (try_two) {
         b->fuse_max = 2;
         b->auto_rows2 = false;
+        auto set = [&](const Shape &sh) {
+            b->bx2 = sh.bx;
+            b->rows2 = sh.rows;
+            return batch_upload(b) == LBM_OK;
+        };
+        auto launch = [&] { return batch_launch_steps(b, 2, nullptr, 0, 0); };
+        std::vector<Shape> cands;
         for (int bx : kTuneWidths2)
             for (int rows : kBatchRowsCand2) {
-                b->bx2 = bx;
-                b->rows2 = rows;
-                if (batch_upload(b) != LBM_OK) continue;
-                const double us =
-                    0.5 * time_launches(b->stream, 3,
-                                        [&] { return batch_launch_steps(b, 2, nullptr, 0, 0); });
-                if (us >= 0 && us < best2) {
-                    best2 = us;
-                    bx2 = bx;
-                    rows2 = rows;
-                }
+                const Shape sh{0.0, bx, rows};
+                if (!set(sh)) continue;
+                const double us = time_launches(b->stream, 3, launch);
+                if (us >= 0) cands.push_back(Shape{us, bx, rows});
             }
+        const Shape best = refine_shapes(b->stream, cands, set, launch);
+        if (best.us >= 0 && best.us < 1e300) {
+            best2 = 0.5 * best.us;
+            bx2 = best.bx;
+            rows2 = best.rows;
+        }
         b->bx2 = bx2;
         b->rows2 = rows2;
     }
