@@ -5,10 +5,16 @@ middle half of the domain (tanh interfaces of width 2, seeded U(+-1e-3) noise)
 of the Carnahan-Starling EOS (a=1, b=4, R=1 convention) at reduced
 temperatures 0.6, 0.7, 0.8 and 0.9, BGK tau = 1, G = -1, eps = 1.73, sigma = 1.
 One bench step advances each of the four lattices by one time step.  The
-library takes two time steps per kernel launch (the two-step pass: read the
-populations once, compute both steps, write once), so the steps are issued in
-pairs, one launch per lattice per pair; an odd step count ends with one
-single-step launch per lattice.  Inputs are resident in HBM before timing.
+four lattices form one batch (the library's batch entry points), so one
+kernel launch covers all four, and the library takes two time steps per
+launch (the two-step pass: read the populations once, compute both steps,
+write once); an odd step count ends with one single-step launch.  The
+launch shape is fixed per storage mode (SLAB_LAUNCH, the fastest of launch
+sweeps of this workload); --launch sets another, --autotune lets the
+library's batch autotuner pick one.
+--one-by-one gives each lattice launches of its own instead; the default line
+carries that rate too (`one_lattice_per_launch`).  Inputs are resident in HBM
+before timing.
 
 Before the timed region at least WARMUP_FLOOR_STEPS untimed steps run (more
 if --warmup asks for more), and the timed steps are enqueued right behind
@@ -17,12 +23,13 @@ the timed region; every step, warm-up included, is checked for a sticky
 domain error after the timed region.
 
 Output: one JSON line.  `value` is lattice updates per second over the timed
-steps (MLUPS).  `roofline` prices the dominant kernel (the two-step pass; the
-single-step sweep with --fusion 1) at the algorithmic bytes of a cell update,
-one read and one write of its populations (144 B in FP64, 72 / 36 / 44 B in
-the reduced-precision modes), times the updates one launch makes (two per
-cell for the two-step pass), over its average launch duration timed with HIP
-events on the library's stream, against the 8 TB/s HBM peak.  Because a
+steps (MLUPS).  `roofline` prices the dominant kernel (the batched two-step
+pass; the batched single step with --fusion 1) at the algorithmic bytes of a
+cell update, one read and one write of its populations (144 B in FP64,
+72 / 36 / 44 B in the reduced-precision modes), times the updates one launch
+makes (two per cell of the four lattices for the two-step pass), over its
+average launch duration timed with HIP events on the library's stream,
+against the 8 TB/s HBM peak.  Because a
 two-step launch reads and writes the populations once for two updates, that
 fraction can exceed 1; `roofline.per_launch_hbm` gives the launch's own
 bytes (one read and one write per cell) against the peak and against a plain
@@ -49,7 +56,8 @@ diag(1, ..., 1, 1/tau, 1/tau) as in the paper's oscillation runs).
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-extras] [--serve-jobs J]
                        [--storage f64|f32|f16|f16l] [--collision bgk|mrt]
-                       [--fusion 1|2] [--workload slab|batch|serve] [--jobs J]
+                       [--fusion 1|2] [--one-by-one] [--launch BX,ROWS] [--autotune]
+                       [--workload slab|batch|serve] [--jobs J]
        python bench.py --copy-calibration   (plain copy kernel for PMC scaling)
 """
 import argparse
@@ -76,30 +84,40 @@ METRIC = "MLUPS/GPU and % HBM roofline (FP64 vs FP32/FP16-shifted); p50/p99 time
 N = 2048
 TEMPS = (0.6, 0.7, 0.8, 0.9)
 WARMUP_FLOOR_STEPS = 200      # untimed steps before any timed region
+# Launch shape (threads per workgroup, segment rows) of the four-lattice batch
+# per steps per launch and storage mode: the fastest of `--launch` sweeps of
+# this workload (two-step pass: FP64 rows 24/32/37 gave 70.5/72.3/71.6 G
+# cell updates/s; FP32 12..20 rows 136, 37 rows 130; FP16 37 rows 183, 24 rows
+# 174; per-cell FP16 32 and 37 rows 134.5, 24 rows 129).  Fixed, so that runs
+# are reproducible and launch the shape the committed counters were taken on;
+# --autotune times the candidates instead (lbm_batch_autotune), which cannot
+# tell shapes 1% apart from run to run.
+SLAB_LAUNCH = {2: {"f64": (256, 32), "f32": (256, 16), "f16": (256, 37), "f16l": (256, 37)},
+               1: {"f64": (256, 5), "f32": (256, 5), "f16": (256, 5), "f16l": (256, 5)}}
 PRECISION_STEPS = 400         # timed steps per reduced-precision mode
 KERNEL_SRC = os.path.join(ROOT, "paper_2003_07968_amd", "csrc", "lbm_kernels.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{storage}_2048.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{storage}_4x2048.json")
 DTYPE = {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
          "f16": "f32 arithmetic, f16-shifted storage",
          "f16l": "f32 arithmetic, f16 storage with per-cell f32 reference"}
 # What limits each dominant kernel, from the committed counter profiles
-# (profiles/sweep2_pass_2048_sq_counters.md, profiles/sweep2_pass_*_2048_traffic.md):
+# (profiles/pass2_4x2048_sq_counters.md, profiles/pass2_*_4x2048_traffic.md):
 # counter-measured HBM bytes against a plain device copy, and VALU issue time
 # (SQ_INSTS_VALU x 4 cycles per wave64 instruction over 1024 SIMDs at 2.4 GHz)
 # against the launch time.
 LIMITER = {
-    ("pass2", "f64"): "hbm and latency: 1.03x the algorithmic bytes at about 5.0 TB/s, a plain "
-                      "device copy's rate but 80% of the best same-pattern stream probe; VALU "
-                      "issue 31% of the launch, 40% of wave-cycles waiting on FP64 dependencies "
-                      "at two waves per SIMD; a third wave per SIMD measured no faster "
-                      "(profiles/sweep2_pass_2048_sq_counters.md)",
-    ("pass2", "f32"): "hbm: 1.02x the algorithmic bytes at about 4.4 TB/s, near a plain device "
-                      "copy's rate; VALU issue 48% of the launch "
-                      "(profiles/sweep2_pass_2048_sq_counters.md)",
-    ("pass2", "f16"): "valu: FP32 arithmetic issue 77% of the launch; HBM about 3.0 TB/s, 1.05x "
-                      "the algorithmic bytes (profiles/sweep2_pass_2048_sq_counters.md)",
-    ("pass2", "f16l"): "valu: FP32 arithmetic issue 84% of the launch; HBM about 2.8 TB/s, 1.06x "
-                       "the algorithmic bytes (profiles/sweep2_pass_2048_sq_counters.md)",
+    ("pass2", "f64"): "hbm and latency: 1.06x the algorithmic bytes at about 5.5 TB/s, above a "
+                      "plain device copy's rate and 87% of the best same-pattern stream probe; "
+                      "VALU issue 33% of the launch, 40% of wave-cycles waiting on FP64 "
+                      "dependencies at two waves per SIMD; a third wave per SIMD measured no "
+                      "faster (profiles/pass2_4x2048_sq_counters.md)",
+    ("pass2", "f32"): "hbm and issue: 1.06x the algorithmic bytes at about 5.2 TB/s, a plain "
+                      "device copy's rate; VALU issue 60% of the launch "
+                      "(profiles/pass2_4x2048_sq_counters.md)",
+    ("pass2", "f16"): "valu: FP32 arithmetic issue 83% of the launch; HBM about 3.4 TB/s, 1.03x "
+                      "the algorithmic bytes (profiles/pass2_4x2048_sq_counters.md)",
+    ("pass2", "f16l"): "valu: FP32 arithmetic issue 92% of the launch; HBM about 3.4 TB/s, 1.12x "
+                       "the algorithmic bytes (profiles/pass2_4x2048_sq_counters.md)",
 }
 
 
@@ -473,66 +491,92 @@ def serving_summary(count):
     return res
 
 
-def run_slab(storage, collision, fusion, steps, warmup):
-    """The four-temperature 2048^2 slab workload in one storage mode: untimed
-    warm-up (at least WARMUP_FLOOR_STEPS steps), then `steps` timed steps
-    enqueued right behind it, bracketed by events on the library's stream
-    (torch's current stream), with events at about every tenth of the paired
-    steps for the spread.  Every lattice's sticky error word is checked after
-    the timed region (it covers the warm-up too)."""
+def run_slab(storage, collision, fusion, steps, warmup, one_by_one=False, shape=None,
+             autotune=False):
+    """The four-temperature 2048^2 slab workload in one storage mode.  The four
+    lattices are advanced together through the library's batch entry points
+    (one launch covers all four lattices, two time steps per launch), with
+    the launch shape `shape` (block_x, seg_rows), by default SLAB_LAUNCH's,
+    or the one the batch autotuner picks; with one_by_one each lattice gets
+    launches of its own instead.  Untimed warm-up (at least
+    WARMUP_FLOOR_STEPS steps), then `steps` timed steps enqueued right behind
+    it, bracketed by events on the library's stream, with events at about
+    every tenth of the paired steps for the spread.  Every lattice's sticky
+    error word is checked after the timed region (it covers the warm-up
+    too)."""
     import torch
     from paper_2003_07968_amd import lbm
     from paper_2003_07968_amd import workloads as W
 
-    lats = []
-    for tr in TEMPS:
-        p, rho0 = W.slab_case(n=N, tr=tr)
-        p["storage"] = W.STORAGE[storage]
-        p["rho_ref"] = W.shift_reference(rho0, storage)
-        p["collision"] = W.COLLISION[collision]
-        lats.append(lbm.Lattice(p, rho0))
-        if fusion is not None:
-            lats[-1].set_fusion(fusion)
-    launch = lats[0].launch()
-    fus = lats[0].fusion()
-    torch.cuda.synchronize()
-    err(f"{storage}: lattices ready, {fus} step(s) per launch, launch shape {launch}")
-
-    def advance(nsteps):
-        for _ in range(nsteps // 2):
+    stream = torch.cuda.Stream()  # graphs of the batch cannot be captured on the null stream
+    with torch.cuda.stream(stream):
+        lats = []
+        for tr in TEMPS:
+            p, rho0 = W.slab_case(n=N, tr=tr)
+            p["storage"] = W.STORAGE[storage]
+            p["rho_ref"] = W.shift_reference(rho0, storage)
+            p["collision"] = W.COLLISION[collision]
+            lats.append(lbm.Lattice(p, rho0))
+            if fusion is not None:
+                lats[-1].set_fusion(fusion)
+        if one_by_one:
+            batch = None
+            launch = list(lats[0].launch())
+            fus = lats[0].fusion()
+        else:
+            batch = lbm.Batch(len(lats))
+            if fusion is not None:
+                batch.set_fusion(fusion)
             for lat in lats:
-                lat.step(2)
-        for _ in range(nsteps % 2):
-            for lat in lats:
-                lat.step(1)
+                batch.add(lat)
+            if autotune:
+                batch.autotune()
+            else:
+                batch.set_launch(fusion or 2, *(shape or SLAB_LAUNCH[fusion or 2][storage]))
+            fus, bx, rows = batch.launch()
+            launch = [bx, rows]
+        torch.cuda.synchronize()
+        err(f"{storage}: lattices ready, {fus} step(s) per launch, "
+            f"{'one lattice per launch' if one_by_one else 'four lattices per launch'}, "
+            f"launch shape {launch}")
 
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    em = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    pairs, odd = divmod(steps, 2)
-    blk = max(1, pairs // 10)
-    marks = []
-    wsteps = max(warmup, WARMUP_FLOOR_STEPS)
-    wsteps += wsteps % 2          # whole pairs, so the timed region starts on a pair
-    t0 = time.perf_counter()
-    advance(wsteps)
-    e0.record(stream)
-    done_pairs = 0
-    while done_pairs < pairs:
-        n = min(blk, pairs - done_pairs)
-        advance(2 * n)
-        done_pairs += n
-        ev = torch.cuda.Event(enable_timing=True)
-        ev.record(stream)
-        marks.append((n, ev))
-    em.record(stream)
-    advance(odd)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for lat in lats:
-        lat.sync()   # raises on a sticky domain error (warm-up or timed steps)
+        def advance(nsteps):
+            if batch is not None:
+                batch.step(nsteps)
+                return
+            for _ in range(nsteps // 2):
+                for lat in lats:
+                    lat.step(2)
+            for _ in range(nsteps % 2):
+                for lat in lats:
+                    lat.step(1)
+
+        e0 = torch.cuda.Event(enable_timing=True)
+        em = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        pairs, odd = divmod(steps, 2)
+        blk = max(1, pairs // 10)
+        marks = []
+        wsteps = max(warmup, WARMUP_FLOOR_STEPS)
+        wsteps += wsteps % 2          # whole pairs, so the timed region starts on a pair
+        t0 = time.perf_counter()
+        advance(wsteps)
+        e0.record(stream)
+        done_pairs = 0
+        while done_pairs < pairs:
+            n = min(blk, pairs - done_pairs)
+            advance(2 * n)
+            done_pairs += n
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            marks.append((n, ev))
+        em.record(stream)
+        advance(odd)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for lat in lats:
+            lat.sync()   # raises on a sticky domain error (warm-up or timed steps)
     gpu_ms = e0.elapsed_time(e1)
     pair_ms = e0.elapsed_time(em)
     block_rates, prev = [], e0
@@ -543,21 +587,43 @@ def run_slab(storage, collision, fusion, steps, warmup):
         prev = ev
     err(f"{storage}: {wsteps} warm-up steps, then {steps} timed steps: {gpu_ms:.2f} ms on the "
         f"stream ({wall * 1e3:.1f} ms wall including the warm-up)")
+    # lattices one launch covers, and launches per pair of steps
+    per_launch = 1 if one_by_one else len(lats)
+    launches_per_pair = len(lats) // per_launch * (1 if fus == 2 else 2)
     if fus == 2 and pairs > 0:
-        kernel, launch_ms = "pass2", pair_ms / (pairs * len(lats))
-        kname = "sweep2_kernel (two steps per launch"
-        timed_launches = pairs * len(lats) + odd * len(lats)
+        kernel, launch_ms = "pass2", pair_ms / (pairs * launches_per_pair)
+        kname = ("sweep2_kernel (two steps per launch" if one_by_one else
+                 "batch2_kernel (two steps per launch, four lattices per launch")
     else:
-        kernel, launch_ms = "step", gpu_ms / (steps * len(lats))
-        kname = "sweep_kernel (one step per launch"
-        timed_launches = steps * len(lats)
+        kernel = "step"
+        launch_ms = gpu_ms / (steps * len(lats) // per_launch)
+        kname = ("sweep_kernel (one step per launch" if one_by_one else
+                 "batch_step_kernel (one step per launch, four lattices per launch")
+    timed_launches = (pairs * launches_per_pair + odd * len(lats) // per_launch
+                      if fus == 2 else steps * len(lats) // per_launch)
     res = {"mlups": N * N * len(lats) * steps / (gpu_ms / 1e3) / 1e6, "gpu_ms": gpu_ms,
            "launch_ms": launch_ms, "kernel": kernel, "kernel_name": kname, "fusion": fus,
-           "launch": launch, "lattices": len(lats), "timed_launches": timed_launches,
-           "warmup_steps": wsteps, "block_rates": block_rates if len(block_rates) >= 5 else []}
-    del lats
+           "launch": launch, "lattices": len(lats), "lattices_per_launch": per_launch,
+           "timed_launches": timed_launches, "warmup_steps": wsteps,
+           "block_rates": block_rates if len(block_rates) >= 5 else []}
+    del batch, lats
     torch.cuda.synchronize()
     return res
+
+
+def one_by_one_rate(batched_mlups, steps=PRECISION_STEPS):
+    """The default workload with launches of one lattice each (the
+    single-lattice two-step kernel, four launches per pair of steps), beside
+    the batched figure of the line."""
+    r = run_slab("f64", "bgk", None, steps, 0, one_by_one=True)
+    upl = 2 if r["kernel"] == "pass2" else 1
+    achieved = BYTES_PER_UPDATE["f64"] * upl * N * N / (r["launch_ms"] / 1e3) / 1e9
+    return {"value": round(r["mlups"], 1), "unit": "MLUPS", "steps": steps,
+            "kernel": r["kernel_name"] + ", f64 storage, bgk)",
+            "kernel_avg_ms": round(r["launch_ms"], 5),
+            "launch_block_x_seg_rows_workgroups": list(r["launch"]),
+            "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
+            "batched_over_one_by_one": round(batched_mlups / r["mlups"], 3)}
 
 
 def precision_rates(f64_mlups):
@@ -569,10 +635,12 @@ def precision_rates(f64_mlups):
         r = run_slab(st, "bgk", None, PRECISION_STEPS, 0)
         upl = 2 if r["kernel"] == "pass2" else 1
         bpu = BYTES_PER_UPDATE[st]
-        achieved = bpu * upl * N * N / (r["launch_ms"] / 1e3) / 1e9
+        achieved = bpu * upl * N * N * r["lattices_per_launch"] / (r["launch_ms"] / 1e3) / 1e9
         out[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS",
                    "speedup_vs_f64": round(r["mlups"] / f64_mlups, 3),
                    "bytes_per_cell_update": bpu, "steps_per_launch": r["fusion"],
+                   "lattices_per_launch": r["lattices_per_launch"],
+                   "launch_block_x_seg_rows": list(r["launch"][:2]),
                    "kernel_avg_ms": round(r["launch_ms"], 5),
                    "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
                    "per_launch_hbm_frac": round(achieved / upl / HBM_PEAK_GBS, 4),
@@ -598,6 +666,12 @@ def main():
                     help="jobs in the reduced serving stream of the default line")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision and serving parts of the default line")
+    ap.add_argument("--one-by-one", action="store_true",
+                    help="slab workload: launches of one lattice each instead of one batch")
+    ap.add_argument("--launch", default=None, metavar="BX,ROWS",
+                    help="slab workload: this batch launch shape instead of SLAB_LAUNCH's")
+    ap.add_argument("--autotune", action="store_true",
+                    help="slab workload: the batch autotuner's launch shape")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -619,19 +693,24 @@ def main():
         run_serve(args)
         return
 
-    res = run_slab(args.storage, args.collision, args.fusion, args.steps, args.warmup)
+    shape = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    res = run_slab(args.storage, args.collision, args.fusion, args.steps, args.warmup,
+                   args.one_by_one, shape, args.autotune)
     n_lat = res["lattices"]
     bpu = BYTES_PER_UPDATE[args.storage]
     kernel = res["kernel"]
     upl = 2 if kernel == "pass2" else 1
     launch_s = res["launch_ms"] / 1e3
+    cells = N * N * res["lattices_per_launch"]   # cells one launch covers
     # the roofline of one cell update: one read and one write of its
     # populations (bpu bytes) at peak bandwidth; a two-step launch makes two
     # updates per cell with one read and one write, so its update rate can
     # exceed that figure
-    achieved = bpu * upl * N * N / launch_s / 1e9
-    launch_gbs = bpu * N * N / launch_s / 1e9
-    traffic = measured_traffic(kernel, args.storage) if args.collision == "bgk" else None
+    achieved = bpu * upl * cells / launch_s / 1e9
+    launch_gbs = bpu * cells / launch_s / 1e9
+    # the committed counter records are of the batched launch
+    counters = args.collision == "bgk" and not args.one_by_one
+    traffic = measured_traffic(kernel, args.storage) if counters else None
     copy_gbs = copy_bandwidth_gbs()
     mlups = res["mlups"]
 
@@ -655,8 +734,12 @@ def main():
             "storage": args.storage, "collision": args.collision,
             "lattices": n_lat, "nx": N, "ny": N,
             "steps_per_launch": res["fusion"],
+            "lattices_per_launch": res["lattices_per_launch"],
             "bytes_per_cell_update": bpu,
-            "launch_block_x_seg_rows_workgroups": list(res["launch"]),
+            "launch_block_x_seg_rows": list(res["launch"][:2]),
+            "launch_from": ("each lattice's default" if args.one_by_one else
+                            "batch autotuner" if args.autotune else
+                            "--launch" if shape else "bench table (SLAB_LAUNCH)"),
             "timed_launches": res["timed_launches"],
             "untimed_warmup_steps": res["warmup_steps"],
         },
@@ -670,11 +753,10 @@ def main():
             "kernel": f"{res['kernel_name']}, {args.storage} storage, {args.collision})",
             "kernel_avg_ms": round(res["launch_ms"], 5),
             "updates_per_launch_per_cell": upl,
-            "limiter": LIMITER.get((kernel, args.storage)) if args.collision == "bgk" else None,
-            "valu": (valu_roofline(kernel, args.storage, res["launch_ms"])
-                     if args.collision == "bgk" else None),
+            "limiter": LIMITER.get((kernel, args.storage)) if counters else None,
+            "valu": valu_roofline(kernel, args.storage, res["launch_ms"]) if counters else None,
             "per_launch_hbm": {
-                "bytes": bpu * N * N,
+                "bytes": bpu * cells,
                 "achieved": round(launch_gbs, 1),
                 "frac": round(launch_gbs / HBM_PEAK_GBS, 4),
                 "copy_kernel_gbs": round(copy_gbs, 1),
@@ -699,6 +781,7 @@ def main():
             "p50": round(float(np.percentile(br, 50)), 1),
             "p90": round(float(np.percentile(br, 90)), 1)}
     if args.storage == "f64" and args.collision == "bgk" and not args.no_extras:
+        out["one_lattice_per_launch"] = one_by_one_rate(mlups)
         out["precision"] = precision_rates(mlups)
         out["serving"] = serving_summary(args.serve_jobs)
     if not args.no_cpu_baseline and args.storage == "f64":

@@ -309,6 +309,22 @@ lbm_status lbm_batch_set_fusion(lbm_batch *b, int32_t steps);
 /* Steps per batched launch in use (1 or 2; -1 for NULL). */
 int32_t lbm_batch_get_fusion(const lbm_batch *b);
 
+/* Fix the batch's launch: `steps` per launch (1 or 2) with workgroups of
+ * block_x threads walking segments of seg_rows rows.  Two-step pass: block_x
+ * 128, 256 or 512, seg_rows >= 1, or 0 for the length chosen at each table
+ * upload (as before lbm_batch_autotune).  Single steps: block_x a multiple of
+ * 64 in 64..512, seg_rows >= 1.  Other values: LBM_ERR_INVALID_ARG, nothing
+ * changed.  For callers that have measured a shape (lbm_batch_autotune) and
+ * want it again without the timing, and for profiling runs that must launch
+ * one known shape.  Results are bitwise the same for every shape.  The next
+ * lbm_batch_step rewrites the table; a shape that needs more workgroups than
+ * a launch may have is reported there. */
+lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t steps, int32_t block_x, int32_t seg_rows);
+
+/* The batch's launch in use: out[0] = steps per launch, out[1] = block_x,
+ * out[2] = seg_rows (the two-step length last chosen or set). */
+lbm_status lbm_batch_get_launch(const lbm_batch *b, int32_t out[3]);
+
 /* Free the host batch object (the handles and the workspace are untouched). */
 void lbm_batch_destroy(lbm_batch *b);
 

@@ -151,6 +151,7 @@ namespace {
 constexpr int kGraphSteps = 8;    // even: a multiple of the steps per launch
 constexpr int kBatchRows2 = 24;   // segment rows of the two-step pass in a batch
 const int kBatchRowsCand2[] = {2, 3, 4, 6, 8, 12, 16, 20, 24, 32, 40};
+constexpr int kBatchRowsMin2 = 2, kBatchRowsMax2 = 48;  // default-length search range
 
 struct Layout {
     size_t err, diag_out, partials, rho_snap, bufA, bufB, total, plane, pitch;
@@ -535,9 +536,9 @@ hipError_t batch_launch_steps(lbm_batch *b, int steps, const long long *ctr, lon
 int batch_fuse(const lbm_batch *b) { return b->fuse_max; }
 
 // Average duration in microseconds of `reps` calls of fn on `stream`, after
-// one untimed call.  Returns a negative value on a HIP error.
+// `warm` untimed calls.  Returns a negative value on a HIP error.
 template <class Fn>
-double time_launches(hipStream_t stream, int reps, Fn &&fn)
+double time_launches(hipStream_t stream, int reps, Fn &&fn, int warm = 1)
 {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1.0;
@@ -546,7 +547,10 @@ double time_launches(hipStream_t stream, int reps, Fn &&fn)
         return -1.0;
     }
     double us = -1.0;
-    if (fn() == hipSuccess && hipEventRecord(e0, stream) == hipSuccess) {
+    bool warmed = true;
+    for (int w = 0; w < warm && warmed; ++w)
+        warmed = fn() == hipSuccess;
+    if (warmed && hipEventRecord(e0, stream) == hipSuccess) {
         bool ok = true;
         for (int r = 0; r < reps && ok; ++r)
             ok = fn() == hipSuccess;
@@ -568,8 +572,9 @@ struct Shape {
 
 // Second pass of a tuner: the kRefine fastest shapes of the first pass (one
 // sample of three launches each) timed again as the best of three samples of
-// ten launches, so that a shape wins by being faster and not by one lucky
-// sample.  set(shape) puts a shape in place (false: it does not fit), fn()
+// twenty launches, each after five untimed ones (a table upload before it
+// leaves the device idle), so that a shape wins by being faster and not by
+// one lucky or cold sample.  set(shape) puts a shape in place (false: it does not fit), fn()
 // makes one launch.  Returns the fastest shape; us < 0 if a launch failed,
 // or 1e300 with no candidates.
 constexpr int kRefine = 3;
@@ -583,7 +588,7 @@ Shape refine_shapes(hipStream_t stream, std::vector<Shape> cands, Set &&set, Fn 
         if (!set(cands[i])) continue;
         double t = 1e300;
         for (int k = 0; k < 3; ++k) {
-            const double us = time_launches(stream, 10, fn);
+            const double us = time_launches(stream, 20, fn, 5);
             if (us < 0) return Shape{-1.0, cands[i].bx, cands[i].rows};
             t = std::min(t, us);
         }
@@ -610,11 +615,13 @@ lbm_status batch_upload(lbm_batch *b)
     const bool two = batch_fuse(b) == 2;
     if (two && b->auto_rows2 && !b->members.empty()) {
         // the segment length that minimises rounds x (rows + 6) over the whole
-        // batch, as for one lattice (the longer one on ties)
+        // batch, as for one lattice (the longer one on ties); every length
+        // from 2 to 48 rows is tried, so that a batch of equal lattices gets
+        // the length that fills whole rounds
         const long long slots =
             (long long)slots_per_cu2(b->storage, b->bx2) * b->members[0]->cus;
         long long best = -1;
-        for (int r : kBatchRowsCand2) {
+        for (int r = kBatchRowsMin2; r <= kBatchRowsMax2; ++r) {
             long long tiles = 0;
             bool ok = true;
             for (const lbm_handle *h : b->members) {
@@ -1269,13 +1276,23 @@ lbm_status lbm_batch_autotune(lbm_batch *b, double out[3])
         };
         auto launch = [&] { return batch_launch_steps(b, 2, nullptr, 0, 0); };
         std::vector<Shape> cands;
-        for (int bx : kTuneWidths2)
+        for (int bx : kTuneWidths2) {
+            // the default length for this width, then the fixed candidates
+            b->bx2 = bx;
+            b->auto_rows2 = true;
+            const bool have_default = batch_upload(b) == LBM_OK;
+            b->auto_rows2 = false;
+            if (have_default) {
+                const double us = time_launches(b->stream, 3, launch);
+                if (us >= 0) cands.push_back(Shape{us, bx, b->rows2});
+            }
             for (int rows : kBatchRowsCand2) {
                 const Shape sh{0.0, bx, rows};
                 if (!set(sh)) continue;
                 const double us = time_launches(b->stream, 3, launch);
                 if (us >= 0) cands.push_back(Shape{us, bx, rows});
             }
+        }
         const Shape best = refine_shapes(b->stream, cands, set, launch);
         if (best.us >= 0 && best.us < 1e300) {
             best2 = 0.5 * best.us;
@@ -1312,6 +1329,47 @@ lbm_status lbm_batch_set_fusion(lbm_batch *b, int32_t steps)
 }
 
 int32_t lbm_batch_get_fusion(const lbm_batch *b) { return b ? batch_fuse(b) : -1; }
+
+lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t steps, int32_t block_x, int32_t seg_rows)
+{
+    if (!b) return LBM_ERR_INVALID_ARG;
+    if (steps == 2) {
+        if ((block_x != 128 && block_x != 256 && block_x != 512) || seg_rows < 0) {
+            b->last_error = "two-step pass: block_x must be 128, 256 or 512 and seg_rows >= 0";
+            return LBM_ERR_INVALID_ARG;
+        }
+        b->bx2 = block_x;
+        b->auto_rows2 = seg_rows == 0;
+        if (seg_rows > 0) b->rows2 = seg_rows;
+    } else if (steps == 1) {
+        if (block_x < 64 || block_x > 512 || block_x % 64 != 0 || seg_rows < 1) {
+            b->last_error = "single steps: block_x must be a multiple of 64 in 64..512 and seg_rows >= 1";
+            return LBM_ERR_INVALID_ARG;
+        }
+        b->bx = block_x;
+        b->rows = seg_rows;
+    } else {
+        b->last_error = "steps per launch must be 1 or 2";
+        return LBM_ERR_INVALID_ARG;
+    }
+    b->fuse_max = steps;
+    b->table_valid = false;
+    if (b->graph_valid) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph_valid = false;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_get_launch(const lbm_batch *b, int32_t out[3])
+{
+    if (!b || !out) return LBM_ERR_INVALID_ARG;
+    const bool two = batch_fuse(b) == 2;
+    out[0] = batch_fuse(b);
+    out[1] = two ? b->bx2 : b->bx;
+    out[2] = two ? b->rows2 : b->rows;
+    return LBM_OK;
+}
 
 void lbm_batch_destroy(lbm_batch *b)
 {

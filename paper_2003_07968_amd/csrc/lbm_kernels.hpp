@@ -948,6 +948,46 @@ __device__ __forceinline__ const BatchEntry &batch_entry(const BatchEntry *__res
     return table[lo];
 }
 
+// A pointer read from the batch table, known to address global memory.
+// Pointers loaded from memory are generic to the compiler, which addresses
+// them with flat instructions (64-bit address arithmetic on the vector ALU,
+// waits on both counters).  Rebuilt from its integer value as a pointer in
+// the global address space, and only then widened to a generic one, it is
+// inferred to be global at every use and gets the same global loads and
+// stores as a kernel argument's pointer.
+template <class T>
+__device__ __forceinline__ T *as_global(T *p)
+{
+    using G = __attribute__((address_space(1))) T *;
+    const G g = (G)(uintptr_t)p;
+    return (T *)g;
+}
+
+// The fields of a lattice's batch entry that a launch uses, copied out of the
+// table once per workgroup.
+struct BatchTile {
+    Coeffs c;
+    Tiles tl;
+    const void *src;
+    void *dst;
+    unsigned long long *err;
+    long long t;
+    int tile;
+};
+template <int BatchEntry::*F, Tiles BatchEntry::*TL>
+__device__ __forceinline__ BatchTile batch_tile(const BatchEntry *__restrict__ table, int nlat,
+                                                int b, long long steps, int parity)
+{
+    const BatchEntry &e = batch_entry<F>(table, nlat, b);
+    return BatchTile{e.c,
+                     e.*TL,
+                     as_global(e.buf[parity]),
+                     as_global(const_cast<void *>(e.buf[parity ^ 1])),
+                     as_global(e.err),
+                     e.t0 + steps,
+                     b - e.*F};
+}
+
 // Where a batched launch starts: the steps and the launches since the batch
 // table was written (the first gives the time, the parity of the second the
 // source buffer).  Eager launches pass them as arguments (d_ctr = nullptr);
@@ -975,10 +1015,9 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(
     long long steps_add, int launches_add)
 {
     const BatchPos pos = batch_pos(d_ctr, steps_add, launches_add);
-    const int b = xcd_tile(blockIdx.x, gridDim.x);
-    const BatchEntry &e = batch_entry<&BatchEntry::tile0>(table, nlat, b);
-    sweep_tile<BX, kStep, PF, FORCE, ST, COLL>(e.buf[pos.parity], (void *)e.buf[pos.parity ^ 1],
-                                               e.c, e.tl, b - e.tile0, e.t0 + pos.steps, e.err,
+    const BatchTile k = batch_tile<&BatchEntry::tile0, &BatchEntry::tl>(
+        table, nlat, xcd_tile(blockIdx.x, gridDim.x), pos.steps, pos.parity);
+    sweep_tile<BX, kStep, PF, FORCE, ST, COLL>(k.src, k.dst, k.c, k.tl, k.tile, k.t, k.err,
                                                Fields{}, nullptr, nullptr);
 }
 
@@ -1423,11 +1462,10 @@ void batch2_kernel(const BatchEntry *__restrict__ table, int nlat,
                    const long long *__restrict__ d_ctr, long long steps_add, int launches_add)
 {
     const BatchPos pos = batch_pos(d_ctr, steps_add, launches_add);
-    const int b = xcd_tile(blockIdx.x, gridDim.x);
-    const BatchEntry &e = batch_entry<&BatchEntry::tile0_2>(table, nlat, b);
-    sweep2_tile<BX, PF, FORCE, ST, COLL, ST != LBM_STORE_F16_LOCAL>(
-        e.buf[pos.parity], (void *)e.buf[pos.parity ^ 1], e.c, e.tl2, b - e.tile0_2,
-        e.t0 + pos.steps, e.err);
+    const BatchTile k = batch_tile<&BatchEntry::tile0_2, &BatchEntry::tl2>(
+        table, nlat, xcd_tile(blockIdx.x, gridDim.x), pos.steps, pos.parity);
+    sweep2_tile<BX, PF, FORCE, ST, COLL, ST != LBM_STORE_F16_LOCAL>(k.src, k.dst, k.c, k.tl,
+                                                                     k.tile, k.t, k.err);
 }
 
 // pull storage: the deviation from w_i rho_ref rounded once, or in the

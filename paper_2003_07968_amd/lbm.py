@@ -140,6 +140,10 @@ def _load():
         lib.lbm_batch_set_fusion.restype = ctypes.c_int
         lib.lbm_batch_get_fusion.argtypes = [B]
         lib.lbm_batch_get_fusion.restype = ctypes.c_int32
+        lib.lbm_batch_set_launch.argtypes = [B, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        lib.lbm_batch_set_launch.restype = ctypes.c_int
+        lib.lbm_batch_get_launch.argtypes = [B, ctypes.POINTER(ctypes.c_int32)]
+        lib.lbm_batch_get_launch.restype = ctypes.c_int
         lib.lbm_batch_destroy.argtypes = [B]
         lib.lbm_batch_destroy.restype = None
         S = ctypes.c_void_p
@@ -170,7 +174,8 @@ EXPORTED = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_sync", "lbm_mome
             "lbm_set_launch", "lbm_set_fusion", "lbm_get_fusion", "lbm_get_launch", "lbm_autotune", "lbm_batch_workspace_bytes",
             "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
             "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_set_fusion",
-            "lbm_batch_get_fusion", "lbm_batch_destroy", "lbm_status_string",
+            "lbm_batch_get_fusion", "lbm_batch_set_launch", "lbm_batch_get_launch",
+            "lbm_batch_destroy", "lbm_status_string",
             "lbm_last_error", "lbm_destroy", "lbm_server_create", "lbm_server_job_bytes",
             "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
             "lbm_server_get_stats", "lbm_server_destroy")
@@ -330,6 +335,16 @@ def lbm_batch_set_fusion(b, steps):
 
 def lbm_batch_get_fusion(b):
     return _load().lbm_batch_get_fusion(b)
+
+
+def lbm_batch_set_launch(b, steps, block_x, seg_rows=0):
+    _check_b(_load().lbm_batch_set_launch(b, int(steps), int(block_x), int(seg_rows)))
+
+
+def lbm_batch_get_launch(b):
+    out = (ctypes.c_int32 * 3)()
+    _check_b(_load().lbm_batch_get_launch(b, out))
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def lbm_batch_destroy(b):
@@ -492,7 +507,8 @@ class Lattice:
 
 
 class Batch:
-    """A group of Lattice objects advanced together, one kernel launch per step."""
+    """A group of Lattice objects advanced together: one kernel launch covers every
+    member, per two time steps (the two-step pass) or per step."""
 
     def __init__(self, capacity, device="cuda", stream=None):
         self.workspace = torch.empty(lbm_batch_workspace_bytes(capacity), dtype=torch.uint8,
@@ -525,6 +541,13 @@ class Batch:
 
     def fusion(self):
         return lbm_batch_get_fusion(self.handle)
+
+    def set_launch(self, steps, block_x, seg_rows=0):
+        lbm_batch_set_launch(self.handle, steps, block_x, seg_rows)
+
+    def launch(self):
+        """(steps per launch, block_x, seg_rows) in use."""
+        return lbm_batch_get_launch(self.handle)
 
     def close(self):
         if self.handle:

@@ -23,9 +23,9 @@ def test_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
     rec = {"kernel": "k", "bytes_per_launch": 12345, "kernel_source_sha256_16": "0123456789abcdef"}
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "traffic_pass2_f64_2048.json").write_text(json.dumps(rec))
+    (prof / "traffic_pass2_f64_4x2048.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE",
-                        str(prof / "traffic_{kernel}_{storage}_2048.json"))
+                        str(prof / "traffic_{kernel}_{storage}_4x2048.json"))
     monkeypatch.setattr(bench, "source_digest", lambda: "0123456789abcdef")
     assert bench.measured_traffic("pass2", "f64") == 12345
     assert bench.measured_traffic("step", "f64") is None      # no file
@@ -44,9 +44,9 @@ def test_valu_roofline_from_the_measured_source(tmp_path, monkeypatch):
            "kernel_source_sha256_16": "0123456789abcdef"}
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "traffic_pass2_f16_2048.json").write_text(json.dumps(rec))
+    (prof / "traffic_pass2_f16_4x2048.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE",
-                        str(prof / "traffic_{kernel}_{storage}_2048.json"))
+                        str(prof / "traffic_{kernel}_{storage}_4x2048.json"))
     monkeypatch.setattr(bench, "source_digest", lambda: "0123456789abcdef")
     v = bench.valu_roofline("pass2", "f16", 0.1)      # 30.72 M instructions in 100 us
     assert v["achieved"] == 307.2 and v["frac"] == 0.5 and v["insts_per_launch"] == 30720000

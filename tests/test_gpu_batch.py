@@ -111,6 +111,38 @@ def test_batch_fusion_switch_midway_and_bad_argument():
     assert batch.fusion() == 2
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16l"])
+def test_batch_set_launch_shapes_and_bad_arguments(storage):
+    # explicit launch shapes, two-step and single-step, switched between
+    # calls (graph replays included): every lattice bitwise equal to its solo
+    # run; bad shapes are rejected and leave the launch as it was
+    require_gpu()
+    cases = _mixed(storage, count=4, seed=12)
+    solo = [gpu_lattice(p, r) for p, r in cases]
+    mates = [gpu_lattice(p, r) for p, r in cases]
+    batch = lbm.Batch(4)
+    for m in mates:
+        batch.add(m)
+    done = 0
+    for steps, bx, rows, n in ((2, 256, 37, 17), (2, 128, 3, 10), (1, 64, 3, 9),
+                               (2, 512, 0, 16), (1, 320, 17, 5), (2, 256, 1, 11)):
+        batch.set_launch(steps, bx, rows)
+        got = batch.launch()
+        assert got[:2] == (steps, bx) and (rows == 0 or got[2] == rows), got
+        batch.step(n)
+        done += n
+        for s in solo:
+            s.step(n)
+        for s, m in zip(solo, mates):
+            assert m.t == done and torch.equal(s.populations(), m.populations()), (steps, bx, rows)
+    before = batch.launch()
+    for bad in ((3, 256, 8), (0, 256, 8), (2, 192, 8), (2, 256, -1), (1, 96, 4), (1, 576, 4),
+                (1, 256, 0)):
+        with pytest.raises(lbm.LbmError):
+            batch.set_launch(*bad)
+        assert batch.launch() == before, bad
+
+
 def test_batch_rejects_mixed_storage_and_full():
     require_gpu()
     (p1, r1), (p2, r2) = _mixed("f64", count=2, seed=5)
