@@ -108,15 +108,15 @@ DTYPE = {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
 LIMITER = {
     ("pass2", "f64"): "hbm and latency: 1.06x the algorithmic bytes at about 5.5 TB/s, above a "
                       "plain device copy's rate and 87% of the best same-pattern stream probe; "
-                      "VALU issue 33% of the launch, 40% of wave-cycles waiting on FP64 "
+                      "VALU issue 33% of the launch, 41% of wave-cycles waiting on FP64 "
                       "dependencies at two waves per SIMD; a third wave per SIMD measured no "
                       "faster (profiles/pass2_4x2048_sq_counters.md)",
-    ("pass2", "f32"): "hbm and issue: 1.06x the algorithmic bytes at about 5.2 TB/s, a plain "
-                      "device copy's rate; VALU issue 60% of the launch "
+    ("pass2", "f32"): "hbm and issue: 1.06x the algorithmic bytes at about 5.3 TB/s, a plain "
+                      "device copy's rate; VALU issue 61% of the launch "
                       "(profiles/pass2_4x2048_sq_counters.md)",
     ("pass2", "f16"): "valu: FP32 arithmetic issue 83% of the launch; HBM about 3.4 TB/s, 1.03x "
                       "the algorithmic bytes (profiles/pass2_4x2048_sq_counters.md)",
-    ("pass2", "f16l"): "valu: FP32 arithmetic issue 92% of the launch; HBM about 3.4 TB/s, 1.12x "
+    ("pass2", "f16l"): "valu: FP32 arithmetic issue 91% of the launch; HBM about 3.1 TB/s, 1.05x "
                        "the algorithmic bytes (profiles/pass2_4x2048_sq_counters.md)",
 }
 

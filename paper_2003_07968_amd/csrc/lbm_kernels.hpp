@@ -1398,10 +1398,9 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
 template <int ST>
 constexpr int kWaves2 = ST == LBM_STORE_F64 ? 2 : 4;
 
-// One tile of the two-step pass: output strip `strip` of row band `seg`.
-// ALT: odd segments walk down the lattice (see walk2), else every segment
-// walks up.
-template <int BX, int PF, int FORCE, int ST, int COLL, bool ALT>
+// One tile of the two-step pass: output strip `strip` of row band `seg`; odd
+// segments walk down the lattice (see walk2).
+template <int BX, int PF, int FORCE, int ST, int COLL>
 __device__ __forceinline__ void sweep2_tile(const void *__restrict__ src_v,
                                             void *__restrict__ dst_v, const Coeffs &c,
                                             const Tiles &tl, int tile, long long t,
@@ -1431,7 +1430,7 @@ __device__ __forceinline__ void sweep2_tile(const void *__restrict__ src_v,
     constexpr uint32_t es = sizeof(E);
     const Cols cols{(uint32_t)x * es, (uint32_t)xm * es, (uint32_t)xp * es};
     unsigned long long bad = ~0ull;
-    if (ALT && (seg & 1))
+    if (seg & 1)
         walk2<BX, PF, FORCE, ST, COLL, -1>((const E *)src_v, (E *)dst_v, c, t, ye - 1, ye - ys,
                                            x, cols, active, valid_b, interior, lds, bad);
     else
@@ -1446,16 +1445,11 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST>)
 void sweep2_kernel(const void *__restrict__ src, void *__restrict__ dst, Coeffs c, Tiles tl,
                    long long t, unsigned long long *__restrict__ err)
 {
-    sweep2_tile<BX, PF, FORCE, ST, COLL, true>(src, dst, c, tl, xcd_tile(blockIdx.x, tl.ntiles), t,
-                                               err);
+    sweep2_tile<BX, PF, FORCE, ST, COLL>(src, dst, c, tl, xcd_tile(blockIdx.x, tl.ntiles), t, err);
 }
 
 // The two-step pass over every lattice of a batch (tiles and counters as in
 // batch_step_kernel; a launch advances two steps and swaps the buffers once).
-// Segments alternate their walk direction in every mode but the per-cell
-// one: on the 256-lattice batch of 64..512-cell droplets its second walk cost
-// 4.5% per launch (83.7 against 87.6 G cell updates/s, same box), more than
-// the re-read halo rows of such small lattices are worth.
 template <int BX, int PF, int FORCE, int ST, int COLL>
 __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(kWaves2<ST>)))
 void batch2_kernel(const BatchEntry *__restrict__ table, int nlat,
@@ -1464,8 +1458,7 @@ void batch2_kernel(const BatchEntry *__restrict__ table, int nlat,
     const BatchPos pos = batch_pos(d_ctr, steps_add, launches_add);
     const BatchTile k = batch_tile<&BatchEntry::tile0_2, &BatchEntry::tl2>(
         table, nlat, xcd_tile(blockIdx.x, gridDim.x), pos.steps, pos.parity);
-    sweep2_tile<BX, PF, FORCE, ST, COLL, ST != LBM_STORE_F16_LOCAL>(k.src, k.dst, k.c, k.tl,
-                                                                     k.tile, k.t, k.err);
+    sweep2_tile<BX, PF, FORCE, ST, COLL>(k.src, k.dst, k.c, k.tl, k.tile, k.t, k.err);
 }
 
 // pull storage: the deviation from w_i rho_ref rounded once, or in the
