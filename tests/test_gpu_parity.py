@@ -3,8 +3,9 @@ inputs: element-by-element, per field, normwise within PARITY_TOL.
 
 Sizes span one to many workgroup tiles, ragged strips and row segments,
 non-square lattices and the 3-cell minimum; the 64 x 64 droplet runs the
-full 5000 steps; the 2048 x 2048 slab (the benchmarked size and launch
-shape) is compared over its first steps at full size."""
+full 5000 steps; the 2048 x 2048 slabs are compared over their first steps
+at full size, alone and as the benchmark runs them (the four lattices in
+one batched launch, in the benchmark's launch shape)."""
 import numpy as np
 import pytest
 import torch
@@ -104,10 +105,9 @@ def test_paper_eos_droplet(oracle):
 
 
 def test_full_size_slab_first_steps(oracle):
-    # 2048 x 2048 slab at T_r = 0.7 in the benchmark's launch configuration
-    # (the default: one two-step launch in the default shape), compared
-    # element by element at t = 2; then one single-step launch (an odd
-    # remainder), compared at t = 3.
+    # 2048 x 2048 slab at T_r = 0.7 stepped alone (the library's default: one
+    # two-step launch in the default shape), compared element by element at
+    # t = 2; then one single-step launch (an odd remainder), compared at t = 3.
     require_gpu()
     log("case slab 2048x2048, 2 + 1 steps")
     p, rho0 = W.slab_case(n=2048, tr=0.7)
@@ -120,6 +120,40 @@ def test_full_size_slab_first_steps(oracle):
         lat.step(n)
         oracle.step(P, f, n)
         assert_parity(gpu_state(lat), oracle_state(oracle, P, f), what=f"t={t}")
+
+
+def test_full_size_batch_as_benchmarked(oracle):
+    # the benchmark's own form: the four 2048 x 2048 slabs (T_r 0.6 .. 0.9)
+    # in one batch, one launch for all four per two steps, in the launch
+    # shape bench.py uses; every lattice compared element by element with the
+    # oracle at t = 2 (one two-step launch) and t = 3 (one single step)
+    require_gpu()
+    import bench
+    from paper_2003_07968_amd import lbm
+    shape = bench.SLAB_LAUNCH[2]["f64"]
+    log(f"case four 2048x2048 slabs as one batch, launch {shape}, 2 + 1 steps")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        cases = [W.slab_case(n=bench.N, tr=tr) for tr in bench.TEMPS]
+        lats = [gpu_lattice(p, rho0) for p, rho0 in cases]
+        batch = lbm.Batch(len(lats))
+        for lat in lats:
+            batch.add(lat)
+        batch.set_launch(2, *shape)
+        assert batch.launch() == (2,) + tuple(shape)
+        refs = []
+        for p, rho0 in cases:
+            P = oracle_params(oracle, p)
+            refs.append((P, oracle.init(P, rho0)))
+        for n, t in ((2, 2), (1, 3)):
+            batch.step(n)
+            torch.cuda.synchronize()
+            for lat, (P, f), tr in zip(lats, refs, bench.TEMPS):
+                oracle.step(P, f, n)
+                assert lat.t == t
+                assert_parity(gpu_state(lat), oracle_state(oracle, P, f), what=f"T_r={tr} t={t}")
+        for lat in lats:
+            lat.sync()
 
 
 @pytest.mark.parametrize("tr", [0.6, 0.7, 0.8, 0.9])
