@@ -32,8 +32,9 @@ average launch duration timed with HIP events on the library's stream,
 against the 8 TB/s HBM peak.  Because a
 two-step launch reads and writes the populations once for two updates, that
 fraction can exceed 1; `roofline.per_launch_hbm` gives the launch's own
-bytes (one read and one write per cell) against the peak and against a plain
-device copy measured in the same run.  `traffic` is the counter-measured HBM
+bytes (one read and one write per cell) against the peak, against a plain
+device copy measured in the same run, and (FP64) against the stream probe: the
+same population access pattern without the arithmetic (lbm_probe_stream).  `traffic` is the counter-measured HBM
 bytes per launch while the kernel source is the one the counters were taken
 on.
 
@@ -107,7 +108,8 @@ DTYPE = {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
 # against the launch time.
 LIMITER = {
     ("pass2", "f64"): "hbm and latency: 1.06x the algorithmic bytes at about 5.5 TB/s, above a "
-                      "plain device copy's rate and 87% of the best same-pattern stream probe; "
+                      "plain device copy's rate and about 94% of the stream probe of the same "
+                      "access pattern (roofline.per_launch_hbm.stream_probe_gbs); "
                       "VALU issue 33% of the launch, 41% of wave-cycles waiting on FP64 "
                       "dependencies at two waves per SIMD; a third wave per SIMD measured no "
                       "faster (profiles/pass2_4x2048_sq_counters.md)",
@@ -194,6 +196,37 @@ def copy_bandwidth_gbs(reps=5):
         best = ms if best is None else min(best, ms)
     del a, b
     return 2 * (1 << 30) / (best / 1e3) / 1e9
+
+
+def stream_probe_gbs(reps=5, launches=10, seg_rows=(4, 8, 16, 32)):
+    """Bandwidth of the step kernels' population access pattern without their
+    arithmetic (lbm_probe_stream: nine FP64 planes pulled as one time step
+    pulls them, non-temporal stores) on a 2048 x 8192 lattice, the cells of
+    one launch of the four-lattice batch: 144 B per cell over the best of
+    `reps` samples of `launches` launches, at the best of the segment
+    lengths, in GB/s."""
+    import torch
+    from paper_2003_07968_amd import lbm
+    nx, ny = N, N * len(TEMPS)
+    n = lbm.lbm_probe_stream_bytes(nx, ny) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    best = None
+    for rows in seg_rows:
+        for _ in range(3):
+            lbm.lbm_probe_stream(a, b, nx, ny, rows)
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(launches):
+                lbm.lbm_probe_stream(a, b, nx, ny, rows)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / launches
+            best = ms if best is None else min(best, ms)
+    del a, b
+    return 144.0 * nx * ny / (best / 1e3) / 1e9
 
 
 def cpu_model():
@@ -712,6 +745,7 @@ def main():
     counters = args.collision == "bgk" and not args.one_by_one
     traffic = measured_traffic(kernel, args.storage) if counters else None
     copy_gbs = copy_bandwidth_gbs()
+    probe_gbs = stream_probe_gbs() if args.storage == "f64" else None
     mlups = res["mlups"]
 
     out = {
@@ -761,6 +795,8 @@ def main():
                 "frac": round(launch_gbs / HBM_PEAK_GBS, 4),
                 "copy_kernel_gbs": round(copy_gbs, 1),
                 "frac_of_copy": round(launch_gbs / copy_gbs, 4),
+                "stream_probe_gbs": round(probe_gbs, 1) if probe_gbs else None,
+                "frac_of_stream_probe": round(launch_gbs / probe_gbs, 4) if probe_gbs else None,
             },
         },
     }

@@ -5,6 +5,7 @@
 // kernels are described in lbm_kernels.hpp; each storage mode's kernels are
 // instantiated in lbm_inst.hip.
 #include "lbm_internal.h"
+#include "lbm_probe.h"
 #include "lbm_kernels.hpp"
 
 #include <mutex>
@@ -735,6 +736,46 @@ hipError_t batch_capture(lbm_batch *b)
     if (e == hipSuccess) b->graph_valid = true;
     return e;
 }
+
+// The step kernels' population traffic with none of their arithmetic: nine
+// FP64 planes in the population layout copied as one time step pulls them,
+// dst_i(x, y) = src_i(x - c_ix, y - c_iy) (periodic), each workgroup walking
+// a segment of rows of a 256-column strip in the XCD-aware tile order, with
+// non-temporal stores.  Its bandwidth is the ceiling of that access pattern.
+__global__ __launch_bounds__(256) void probe_stream9(const double *__restrict__ src,
+                                                     double *__restrict__ dst, int nx, int ny,
+                                                     size_t plane, size_t pitch, int nstrips,
+                                                     int nseg)
+{
+    const int tile = lbmk::xcd_tile(blockIdx.x, nstrips * nseg);
+    const int seg = tile / nstrips, strip = tile - seg * nstrips;
+    const int x = strip * 256 + (int)threadIdx.x;
+    if (x >= nx) return;  // no barriers below
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ys = (int)((long long)seg * ny / nseg), ye = (int)((long long)(seg + 1) * ny / nseg);
+    for (int y = ys; y < ye; ++y) {
+        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        const double *r = src + (size_t)y * pitch;
+        const double *rm = src + (size_t)ym * pitch;
+        const double *rp = src + (size_t)yp * pitch;
+        double v[9];
+        v[0] = r[x];
+        v[1] = r[plane + xm];
+        v[2] = rm[2 * plane + x];
+        v[3] = r[3 * plane + xp];
+        v[4] = rp[4 * plane + x];
+        v[5] = rm[5 * plane + xm];
+        v[6] = rm[6 * plane + xp];
+        v[7] = rp[7 * plane + xp];
+        v[8] = rp[8 * plane + xm];
+        double *o = dst + (size_t)y * pitch;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            __builtin_nontemporal_store(v[i], o + (size_t)i * plane + x);
+    }
+}
+
+constexpr size_t kProbePlaneAlign = 16;  // doubles: rows on 128-byte boundaries
 }  // namespace
 
 extern "C" {
@@ -1394,6 +1435,27 @@ const char *lbm_status_string(lbm_status s)
 const char *lbm_last_error(const lbm_handle *h) { return h ? h->last_error.c_str() : ""; }
 
 void lbm_destroy(lbm_handle *h) { delete h; }
+
+size_t lbm_probe_stream_bytes(int32_t nx, int32_t ny)
+{
+    if (nx < 3 || ny < 3) return 0;
+    return kQ * round_up((size_t)nx, kProbePlaneAlign) * (size_t)ny * sizeof(double);
+}
+
+lbm_status lbm_probe_stream(const double *d_src, double *d_dst, int32_t nx, int32_t ny,
+                            int32_t seg_rows, void *hip_stream)
+{
+    if (!d_src || !d_dst || d_src == d_dst || nx < 3 || ny < 3 || seg_rows < 1)
+        return LBM_ERR_INVALID_ARG;
+    const size_t plane = round_up((size_t)nx, kProbePlaneAlign);
+    const int nstrips = (nx + 255) / 256;
+    const int nseg = (ny + seg_rows - 1) / seg_rows;
+    if ((long long)nstrips * nseg > kMaxTiles) return LBM_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(probe_stream9, dim3(nstrips * nseg), dim3(256), 0,
+                       (hipStream_t)hip_stream, d_src, d_dst, nx, ny, plane, kQ * plane, nstrips,
+                       nseg);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_DEVICE;
+}
 
 }  // extern "C"
 

@@ -146,6 +146,11 @@ def _load():
         lib.lbm_batch_get_launch.restype = ctypes.c_int
         lib.lbm_batch_destroy.argtypes = [B]
         lib.lbm_batch_destroy.restype = None
+        lib.lbm_probe_stream_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        lib.lbm_probe_stream_bytes.restype = ctypes.c_size_t
+        lib.lbm_probe_stream.argtypes = [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         _VP]
+        lib.lbm_probe_stream.restype = ctypes.c_int
         S = ctypes.c_void_p
         DP = ctypes.POINTER(ctypes.c_double)
         lib.lbm_server_create.argtypes = [ctypes.POINTER(lbm_server_config), _VP,
@@ -178,7 +183,8 @@ EXPORTED = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_sync", "lbm_mome
             "lbm_batch_destroy", "lbm_status_string",
             "lbm_last_error", "lbm_destroy", "lbm_server_create", "lbm_server_job_bytes",
             "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
-            "lbm_server_get_stats", "lbm_server_destroy")
+            "lbm_server_get_stats", "lbm_server_destroy", "lbm_probe_stream_bytes",
+            "lbm_probe_stream")
 
 
 def make_params(p: dict) -> lbm_params:
@@ -345,6 +351,26 @@ def lbm_batch_get_launch(b):
     out = (ctypes.c_int32 * 3)()
     _check_b(_load().lbm_batch_get_launch(b, out))
     return int(out[0]), int(out[1]), int(out[2])
+
+
+def lbm_probe_stream_bytes(nx, ny):
+    return int(_load().lbm_probe_stream_bytes(int(nx), int(ny)))
+
+
+def lbm_probe_stream(src, dst, nx, ny, seg_rows=32, stream=None):
+    """One pulled copy of nine FP64 population planes (the step kernels'
+    access pattern without their arithmetic) between two device tensors of
+    lbm_probe_stream_bytes(nx, ny) bytes, on `stream` (default: torch's
+    current stream)."""
+    stream = stream if stream is not None else torch.cuda.current_stream(src.device)
+    need = lbm_probe_stream_bytes(nx, ny)
+    for t in (src, dst):
+        if t.device.type != "cuda" or t.numel() * t.element_size() < need:
+            raise ValueError(f"probe buffers must be device tensors of at least {need} bytes")
+    st = _load().lbm_probe_stream(_dev_ptr(src), _dev_ptr(dst), int(nx), int(ny), int(seg_rows),
+                                  ctypes.c_void_p(stream.cuda_stream))
+    if st != LBM_OK:
+        raise LbmError(st)
 
 
 def lbm_batch_destroy(b):
