@@ -132,9 +132,11 @@ def source_digest():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def counter_record(kernel, storage):
+def counter_record(kernel, storage, shape=None):
     """The committed rocprofv3 counter record of `kernel` ("pass2" or "step")
-    in this storage mode, if it was taken on the current kernel source."""
+    in this storage mode, if it was taken on the current kernel source and,
+    when `shape` (block_x, seg_rows) is given, at that launch shape (the
+    traffic of a launch depends on its segments' halo rows)."""
     path = TRAFFIC_FILE.format(kernel=kernel, storage=storage)
     if not os.path.exists(path):
         return None
@@ -142,22 +144,24 @@ def counter_record(kernel, storage):
         rec = json.load(fh)
     if rec.get("kernel_source_sha256_16") != source_digest():
         return None
+    if shape is not None and list(rec.get("launch_block_x_seg_rows") or []) != list(shape):
+        return None
     return rec
 
 
-def measured_traffic(kernel, storage):
+def measured_traffic(kernel, storage, shape=None):
     """HBM bytes per launch from the committed counter runs, or None."""
-    rec = counter_record(kernel, storage)
+    rec = counter_record(kernel, storage, shape)
     return rec.get("bytes_per_launch") if rec else None
 
 
-def valu_roofline(kernel, storage, launch_ms):
+def valu_roofline(kernel, storage, launch_ms, shape=None):
     """VALU issue of one launch against the chip's issue rate: the launch's
     wave64 VALU instructions (SQ_INSTS_VALU of the committed counter run; the
     count is fixed by the code and the launch shape) over its live average
     duration, against 1024 SIMDs x 2.4 GHz / 4 cycles per wave64 FP32 or FP64
     instruction = 614.4 G instructions/s.  None without a current record."""
-    rec = counter_record(kernel, storage)
+    rec = counter_record(kernel, storage, shape)
     if not rec or not rec.get("valu_insts_per_launch"):
         return None
     achieved = rec["valu_insts_per_launch"] / (launch_ms / 1e3) / 1e9
@@ -677,7 +681,7 @@ def precision_rates(f64_mlups):
                    "kernel_avg_ms": round(r["launch_ms"], 5),
                    "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
                    "per_launch_hbm_frac": round(achieved / upl / HBM_PEAK_GBS, 4),
-                   "valu": valu_roofline(r["kernel"], st, r["launch_ms"]),
+                   "valu": valu_roofline(r["kernel"], st, r["launch_ms"], r["launch"][:2]),
                    "limiter": LIMITER.get((r["kernel"], st))}
     return out
 
@@ -743,7 +747,7 @@ def main():
     launch_gbs = bpu * cells / launch_s / 1e9
     # the committed counter records are of the batched launch
     counters = args.collision == "bgk" and not args.one_by_one
-    traffic = measured_traffic(kernel, args.storage) if counters else None
+    traffic = measured_traffic(kernel, args.storage, res["launch"][:2]) if counters else None
     copy_gbs = copy_bandwidth_gbs()
     probe_gbs = stream_probe_gbs() if args.storage == "f64" else None
     mlups = res["mlups"]
@@ -788,7 +792,8 @@ def main():
             "kernel_avg_ms": round(res["launch_ms"], 5),
             "updates_per_launch_per_cell": upl,
             "limiter": LIMITER.get((kernel, args.storage)) if counters else None,
-            "valu": valu_roofline(kernel, args.storage, res["launch_ms"]) if counters else None,
+            "valu": (valu_roofline(kernel, args.storage, res["launch_ms"], res["launch"][:2])
+                     if counters else None),
             "per_launch_hbm": {
                 "bytes": bpu * cells,
                 "achieved": round(launch_gbs, 1),

@@ -20,7 +20,8 @@ def test_more_than_one_gpu_is_refused():
 def test_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
-    rec = {"kernel": "k", "bytes_per_launch": 12345, "kernel_source_sha256_16": "0123456789abcdef"}
+    rec = {"kernel": "k", "bytes_per_launch": 12345, "kernel_source_sha256_16": "0123456789abcdef",
+           "launch_block_x_seg_rows": [256, 32]}
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "traffic_pass2_f64_4x2048.json").write_text(json.dumps(rec))
@@ -28,6 +29,8 @@ def test_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
                         str(prof / "traffic_{kernel}_{storage}_4x2048.json"))
     monkeypatch.setattr(bench, "source_digest", lambda: "0123456789abcdef")
     assert bench.measured_traffic("pass2", "f64") == 12345
+    assert bench.measured_traffic("pass2", "f64", (256, 32)) == 12345
+    assert bench.measured_traffic("pass2", "f64", [256, 37]) is None  # another launch shape
     assert bench.measured_traffic("step", "f64") is None      # no file
     monkeypatch.setattr(bench, "source_digest", lambda: "fedcba9876543210")
     assert bench.measured_traffic("pass2", "f64") is None     # kernel changed since
