@@ -90,3 +90,16 @@ def test_null_handle_rejected_by_host_entry_points(lib):
     assert lib.lbm_set_launch(None, 256, 8) == lbm.LBM_ERR_INVALID_ARG
     assert lib.lbm_get_launch(None, out) == lbm.LBM_ERR_INVALID_ARG
     assert lib.lbm_step(None, 1) == lbm.LBM_ERR_INVALID_ARG
+
+
+def test_probe_sizes_and_validation(lib):
+    # the bandwidth probe's buffer size (nine planes of nx rounded up to 16
+    # FP64 values, one per row) and its argument checks, before any launch
+    from paper_2003_07968_amd import lbm
+    assert lib.lbm_probe_stream_bytes(2048, 8192) == 9 * 2048 * 8192 * 8
+    assert lib.lbm_probe_stream_bytes(37, 23) == 9 * 48 * 23 * 8
+    assert lib.lbm_probe_stream_bytes(2, 10) == 0 and lib.lbm_probe_stream_bytes(10, 2) == 0
+    a, b = ctypes.c_void_p(16), ctypes.c_void_p(32)   # never dereferenced: rejected first
+    for args in ((None, b, 16, 16, 4), (a, None, 16, 16, 4), (a, a, 16, 16, 4),
+                 (a, b, 2, 16, 4), (a, b, 16, 2, 4), (a, b, 16, 16, 0), (a, b, 16, 10**7, 1)):
+        assert lib.lbm_probe_stream(*args, None) == lbm.LBM_ERR_INVALID_ARG, args
