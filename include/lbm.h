@@ -294,16 +294,19 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 /* Choose the batch's workgroup width and segment length by timing candidate
  * shapes on the batch as it is (state unchanged, as lbm_autotune): single
  * steps, and the two-step pass unless lbm_batch_set_fusion(b, 1) was called
- * (segments of 2..40 rows); the faster per time step is kept
- * (lbm_batch_get_fusion tells which).  Synchronous; out (may be NULL):
- * block_x, seg_rows, microseconds per time step. */
+ * (each width's default length and segments of 2..40 rows).  Every shape is
+ * timed over a few launches, the fastest three again over longer samples;
+ * the faster form per time step is kept (lbm_batch_get_fusion tells which).
+ * Shapes within about 1% of each other may swap places between calls.
+ * Synchronous; out (may be NULL): block_x, seg_rows, microseconds per time
+ * step. */
 lbm_status lbm_batch_autotune(lbm_batch *b, double out[3]);
 
 /* Time steps per batched launch: 2 (the default) or 1.  Results are bitwise
  * the same either way.  The next lbm_batch_step rewrites the table.
- * Until lbm_batch_autotune is called, the two-step segment length is chosen
- * at each table upload to fill whole rounds of the workgroups the device runs
- * at once (2..40 rows over all members). */
+ * Until lbm_batch_autotune or lbm_batch_set_launch is called, the two-step
+ * segment length is chosen at each table upload to fill whole rounds of the
+ * workgroups the device runs at once (2..48 rows over all members). */
 lbm_status lbm_batch_set_fusion(lbm_batch *b, int32_t steps);
 
 /* Steps per batched launch in use (1 or 2; -1 for NULL). */
