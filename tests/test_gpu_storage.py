@@ -53,6 +53,47 @@ def test_matches_storage_emulating_oracle(oracle, storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "f16l"])
+def test_full_size_batch_matches_storage_emulating_oracle(oracle, storage):
+    # the benchmark's precision part in its own form: the four 2048 x 2048
+    # slabs in one batch, in the launch shape bench.py uses for this storage
+    # mode, one batched two-step launch (t = 2) and one single step (t = 3),
+    # every lattice against the storage-emulating oracle
+    require_gpu()
+    import bench
+    from paper_2003_07968_amd import lbm
+    shape = bench.SLAB_LAUNCH[2][storage]
+    log(f"case four 2048x2048 slabs as one batch, storage={storage}, launch {shape}")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        cases = []
+        for tr in bench.TEMPS:
+            p, rho0 = W.slab_case(n=bench.N, tr=tr)
+            p["storage"] = W.STORAGE[storage]
+            p["rho_ref"] = W.shift_reference(rho0, storage)
+            cases.append((p, rho0))
+        lats = [gpu_lattice(p, rho0) for p, rho0 in cases]
+        batch = lbm.Batch(len(lats))
+        for lat in lats:
+            batch.add(lat)
+        batch.set_launch(2, *shape)
+        refs = []
+        for p, rho0 in cases:
+            P = oracle_params(oracle, p)
+            refs.append((P, oracle.init(P, rho0)))
+        for n, t in ((2, 2), (1, 3)):
+            batch.step(n)
+            torch.cuda.synchronize()
+            for lat, (P, f), tr in zip(lats, refs, bench.TEMPS):
+                oracle.step(P, f, n)
+                errs = parity_errors(gpu_state(lat), oracle_state(oracle, P, f))
+                log(f"  T_r={tr} t={t}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+                for k, v in errs.items():
+                    assert v <= EMULATED_TOL[storage], (tr, t, k, v)
+        for lat in lats:
+            lat.sync()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16l"])
 def test_initial_state_is_rounded_equilibrium(oracle, storage):
     require_gpu()
     p, rho0 = W.droplet_64(seed=2)
