@@ -122,19 +122,23 @@ def test_full_size_slab_first_steps(oracle):
         assert_parity(gpu_state(lat), oracle_state(oracle, P, f), what=f"t={t}")
 
 
-def test_full_size_batch_as_benchmarked(oracle):
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_full_size_batch_as_benchmarked(oracle, collision):
     # the benchmark's own form: the four 2048 x 2048 slabs (T_r 0.6 .. 0.9)
     # in one batch, one launch for all four per two steps, in the launch
-    # shape bench.py uses; every lattice compared element by element with the
-    # oracle at t = 2 (one two-step launch) and t = 3 (one single step)
+    # shape bench.py uses (BGK, the default line, and MRT, --collision mrt);
+    # every lattice compared element by element with the oracle at t = 2 (one
+    # two-step launch) and t = 3 (one single step)
     require_gpu()
     import bench
     from paper_2003_07968_amd import lbm
     shape = bench.SLAB_LAUNCH[2]["f64"]
-    log(f"case four 2048x2048 slabs as one batch, launch {shape}, 2 + 1 steps")
+    log(f"case four 2048x2048 slabs as one batch, {collision}, launch {shape}, 2 + 1 steps")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         cases = [W.slab_case(n=bench.N, tr=tr) for tr in bench.TEMPS]
+        for p, _ in cases:
+            p["collision"] = W.COLLISION[collision]
         lats = [gpu_lattice(p, rho0) for p, rho0 in cases]
         batch = lbm.Batch(len(lats))
         for lat in lats:
