@@ -160,6 +160,35 @@ def test_full_size_batch_as_benchmarked(oracle, collision):
             lat.sync()
 
 
+def test_full_size_batch_graph_replays(oracle):
+    # the benchmarked form over 96 steps: twelve replays of the batch's
+    # captured eight-step graph (four two-step launches each) at full size,
+    # every lattice compared with the oracle at the end
+    require_gpu()
+    import bench
+    from paper_2003_07968_amd import lbm
+    shape = bench.SLAB_LAUNCH[2]["f64"]
+    log(f"case four 2048x2048 slabs as one batch, launch {shape}, 96 steps in graphs")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        cases = [W.slab_case(n=bench.N, tr=tr) for tr in bench.TEMPS]
+        lats = [gpu_lattice(p, rho0) for p, rho0 in cases]
+        batch = lbm.Batch(len(lats))
+        for lat in lats:
+            batch.add(lat)
+        batch.set_launch(2, *shape)
+        batch.step(96)
+        torch.cuda.synchronize()
+        for lat, (p, rho0), tr in zip(lats, cases, bench.TEMPS):
+            P = oracle_params(oracle, p)
+            f = oracle.init(P, rho0)
+            oracle.step(P, f, 96)
+            assert lat.t == 96
+            assert_parity(gpu_state(lat), oracle_state(oracle, P, f), what=f"T_r={tr} t=96")
+        for lat in lats:
+            lat.sync()
+
+
 @pytest.mark.parametrize("tr", [0.6, 0.7, 0.8, 0.9])
 def test_full_size_slab_conservation(tr):
     # 2048 x 2048 slab: mass and total momentum are conserved to rounding over
