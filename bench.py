@@ -108,9 +108,9 @@ DTYPE = {"f64": "f64", "f32": "f32 (FP32-shifted storage)",
 # against the launch time.
 LIMITER = {
     ("pass2", "f64"): "hbm and latency: 1.06x the algorithmic bytes at about 5.5 TB/s, above a "
-                      "plain device copy's rate and about 94% of the stream probe of the same "
+                      "plain device copy's rate and about 95% of the stream probe of the same "
                       "access pattern (roofline.per_launch_hbm.stream_probe_gbs); "
-                      "VALU issue 33% of the launch, 41% of wave-cycles waiting on FP64 "
+                      "VALU issue 33% of the launch, 40% of wave-cycles waiting on FP64 "
                       "dependencies at two waves per SIMD; a third wave per SIMD measured no "
                       "faster (profiles/pass2_4x2048_sq_counters.md)",
     ("pass2", "f32"): "hbm and issue: 1.06x the algorithmic bytes at about 5.3 TB/s, a plain "
@@ -118,7 +118,7 @@ LIMITER = {
                       "(profiles/pass2_4x2048_sq_counters.md)",
     ("pass2", "f16"): "valu: FP32 arithmetic issue 83% of the launch; HBM about 3.4 TB/s, 1.03x "
                       "the algorithmic bytes (profiles/pass2_4x2048_sq_counters.md)",
-    ("pass2", "f16l"): "valu: FP32 arithmetic issue 91% of the launch; HBM about 3.1 TB/s, 1.05x "
+    ("pass2", "f16l"): "valu: FP32 arithmetic issue 90% of the launch; HBM about 3.2 TB/s, 1.05x "
                        "the algorithmic bytes (profiles/pass2_4x2048_sq_counters.md)",
 }
 

@@ -1038,13 +1038,14 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(
 //   turns A's row m - 3 into rho and psi (psi to LDS; barrier 1),
 //   collides A's row m - 4 and hands it to B (barrier 2),
 //   pulls B's row m - 5 and turns it into rho and psi (psi to LDS; barrier 3),
-//   pulls B's row m - 6 again, collides it and stores it.
+//   collides B's row m - 6, whose pulled populations it kept in registers
+//   since the previous iteration, and stores it.
 // psi rows live in LDS rings of three rows (slot = iteration mod 3); the
 // force reads its 3 x 3 window there.  Of A's post-collision values only the
 // populations that B pulls from a neighbouring lane go through LDS, each kept
-// as long as B reads it: those pulled from the walk's next row (lattice row
-// r + 1 walking up) two iterations, 1 and 3 (row r) three, those pulled from
-// the walk's previous row (r - 1 walking up) four.  Populations 0 and the
+// until B has pulled it: those pulled from the walk's next row (lattice row
+// r + 1 walking up) for one iteration, 1 and 3 (row r) two, those pulled from
+// the walk's previous row (r - 1 walking up) three.  Populations 0 and the
 // two vertical ones come from the own lane and stay in registers.  Register
 // sets rotate with period 6 (the loop is unrolled six times).
 //
@@ -1063,13 +1064,15 @@ __global__ __launch_bounds__(BX, (kMinWaves<ST, COLL>)) void batch_step_kernel(
 template <class R, int BX, bool LOC>
 struct Pass2Lds {
     R psi_a[3][BX], psi_b[3][BX];  // psi of A's and B's rows
-    R pa[2][2][BX];                // diagonal pair B pulls from the walk's next row
-    R p13[3][2][BX];               // populations 1, 3
-    R pb[4][2][BX];                // diagonal pair B pulls from the walk's previous row
+    // A's post-collision populations that B pulls from a neighbouring lane,
+    // one slot per row that is still to be pulled
+    R pa[2][BX];                   // diagonal pair from the walk's next row
+    R p13[2][2][BX];               // populations 1, 3 of the current row
+    R pb[3][2][BX];                // diagonal pair from the walk's previous row
     // per-cell mode: the reference R of A's input rows (exchanged for the
     // neighbours' values) and the new R of A's output rows (B reads it for
-    // rows r - 1, r, r + 1, so four rows live at once)
-    float r_in[LOC ? 2 : 1][BX], r_out[LOC ? 4 : 1][BX];
+    // rows r - 1, r, r + 1)
+    float r_in[LOC ? 2 : 1][BX], r_out[LOC ? 3 : 1][BX];
 };
 
 // Halo columns of the two-step pass on each side of its output strip.
@@ -1126,7 +1129,7 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     // population 0 and the vertical ones of A's last post-collision rows:
     // hb pulled from the walk's previous row (2 walking up, 4 walking down),
     // ha from its next row
-    R h0[3], hb[6], ha[2];
+    R h0[2], hb[3], ha;
     // populations B pulls from the walk's previous row (kB) and next row
     // (kA): the vertical one, then the diagonal pair in the order of their
     // LDS slots (previous row: from lane txm, from txp; next row: from txp,
@@ -1138,6 +1141,11 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
     Tri<R> ta[3];
     R ra[2];
     RefPair<R> rl[2];
+    // B's pulled populations of the row turned into psi (per-cell mode:
+    // rebuilt as deviations from its R, kept in rb), held for the collision
+    // of that row at the next iteration
+    R gb[2][kQ];
+    R rb[2];
     const bool first = tx == BX - kHalo2;  // column position 0, the leftmost
     // R at x - 1, x, x + 1 from a lane's own and side values and an LDS row
     auto tri_from = [&](const RefPair<R> &v, const float *buf) {
@@ -1161,12 +1169,14 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
             fa[k][i] = R(0);
     }
     rho_a[0] = rho_a[1] = rho_b[0] = rho_b[1] = R(0);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        hb[k] = R(0);
-    h0[0] = h0[1] = h0[2] = R(0);
-    ha[0] = ha[1] = R(0);
+    hb[0] = hb[1] = hb[2] = R(0);
+    h0[0] = h0[1] = R(0);
+    ha = R(0);
     ra[0] = ra[1] = R(0);
+    rb[0] = rb[1] = R(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+        gb[0][i] = gb[1][i] = R(0);
     // prologue: A's populations of rows -3 .. -4 + PF
 #pragma unroll
     for (int p = 0; p < PF; ++p)
@@ -1256,53 +1266,50 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
                     err += dev - (R)X;
                     g[i] = (R)X;
                 }
-                L.r_out[m & 3][tx] = (float)(ref_cur + (sd + err));
+                L.r_out[J % 3][tx] = (float)(ref_cur + (sd + err));
             }
             auto rd = [&](int i) { return LOC ? g[i] : (R)(E)g[i]; };
-            h0[J % 3] = rd(0);
-            hb[J] = rd(kB0);
-            ha[J % 2] = rd(kA0);
-            L.p13[J % 3][0][tx] = rd(1);
-            L.p13[J % 3][1][tx] = rd(3);
-            L.pb[m & 3][0][tx] = rd(kB1);
-            L.pb[m & 3][1][tx] = rd(kB2);
-            L.pa[J % 2][0][tx] = rd(kA1);
-            L.pa[J % 2][1][tx] = rd(kA2);
+            h0[J % 2] = rd(0);
+            hb[J % 3] = rd(kB0);
+            ha = rd(kA0);
+            L.p13[J % 2][0][tx] = rd(1);
+            L.p13[J % 2][1][tx] = rd(3);
+            L.pb[J % 3][0][tx] = rd(kB1);
+            L.pb[J % 3][1][tx] = rd(kB2);
+            L.pa[0][tx] = rd(kA1);
+            L.pa[1][tx] = rd(kA2);
         }
         __syncthreads();
-        // B's pulled populations of row m - 5 - back (back = 0: the row turned
-        // into psi now, back = 1: the row collided now); A's row q was written
-        // at iteration q + 4
-        auto pull_b = [&](auto backc, R g[kQ]) {
-            constexpr int b = decltype(backc)::value;
-            constexpr int s3r = (J + 5 - b) % 3;
-            // walk rows: ahead (written at m - b, two slots), current (m - 1
-            // - b), back (m - 2 - b, four LDS slots, six register slots);
-            // populations 4, 7, 8 come from lattice row r + 1, 2, 5, 6 from
-            // r - 1, and a population moving right (5, 8) from lane txm
-            constexpr int sa = (J + 2 - b) % 2, sh = (J + 10 - b) % 6;
-            const int sl = (m + 2 - b) & 3;
-            g[kA0] = ha[sa];
-            g[kA1] = L.pa[sa][0][txp];
-            g[kA2] = L.pa[sa][1][txm];
-            g[kB0] = hb[sh];
-            g[kB1] = L.pb[sl][0][txm];
-            g[kB2] = L.pb[sl][1][txp];
-            g[0] = h0[s3r];
-            g[1] = L.p13[s3r][0][txm];
-            g[3] = L.p13[s3r][1][txp];
+        // B's pulled populations of row m - 5, the row turned into psi now;
+        // A's row q was written at iteration q + 4
+        auto pull_b = [&](R g[kQ]) {
+            // walk rows: ahead (written at m), current (m - 1, slot (J + 1) %
+            // 2), back (m - 2, slot (J + 1) % 3); populations 4, 7, 8 come
+            // from lattice row r + 1, 2, 5, 6 from r - 1, and a population
+            // moving right (5, 8) from lane txm
+            constexpr int sc = (J + 1) % 2, sb = (J + 1) % 3;
+            g[kA0] = ha;
+            g[kA1] = L.pa[0][txp];
+            g[kA2] = L.pa[1][txm];
+            g[kB0] = hb[sb];
+            g[kB1] = L.pb[sb][0][txm];
+            g[kB2] = L.pb[sb][1][txp];
+            g[0] = h0[sc];
+            g[1] = L.p13[sc][0][txm];
+            g[3] = L.p13[sc][1][txp];
         };
         // step B: rho and psi of row m - 5
         if constexpr (DO_BPSI) {
-            R g[kQ];
-            pull_b(std::integral_constant<int, 0>{}, g);
+            R *g = gb[J % 2];
+            pull_b(g);
             R ref_b = gref;
             if constexpr (LOC) {
                 // the walk's next, current and previous rows were handed
                 // over at m, m - 1, m - 2
-                const Tri<R> C = tri_lds(L.r_out[(m + 3) & 3]);
-                recon(g, tri_lds(L.r_out[(m + 2) & 3]), C, tri_lds(L.r_out[m & 3]));
+                const Tri<R> C = tri_lds(L.r_out[(J + 2) % 3]);
+                recon(g, tri_lds(L.r_out[(J + 1) % 3]), C, tri_lds(L.r_out[J % 3]));
                 ref_b = C.o;
+                rb[J % 2] = ref_b;
             }
             R psi;
             const bool ok = rho_psi<FORCE, R>(g, ref_b, P, rho_b[J % 2], psi);
@@ -1310,18 +1317,14 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
             L.psi_b[J % 3][tx] = psi;
         }
         __syncthreads();
-        // step B: collision of row m - 6 and its store
+        // step B: collision of row m - 6 and its store, from the populations
+        // its psi pass pulled at the previous iteration
         if constexpr (DO_BCOL) {
             R g[kQ];
-            pull_b(std::integral_constant<int, 1>{}, g);
-            R ref_cur = gref;
-            if constexpr (LOC) {
-                // the walk's next, current and previous rows were handed
-                // over at m - 1, m - 2, m - 3
-                const Tri<R> C = tri_lds(L.r_out[(m + 2) & 3]);
-                recon(g, tri_lds(L.r_out[(m + 1) & 3]), C, tri_lds(L.r_out[(m + 3) & 3]));
-                ref_cur = C.o;
-            }
+#pragma unroll
+            for (int i = 0; i < kQ; ++i)
+                g[i] = gb[(J + 1) % 2][i];
+            const R ref_cur = LOC ? rb[(J + 1) % 2] : gref;
             R Fx = R(0), Fy = R(0);
             if (FORCE) {
                 // walk rows m - 7 (back), m - 6 (current), m - 5 (ahead)
@@ -1387,14 +1390,14 @@ __device__ __forceinline__ void walk2(const typename Store<ST>::E *__restrict__ 
 }
 
 
-// Waves per SIMD the two-step pass is compiled for.  FP64 runs at two (178
-// VGPRs with BGK and the force).  Three fit in LDS (50 kB per workgroup) and,
-// with the density summed again at the collision instead of kept, in 168
-// VGPRs with a few loop-invariant reloads, but gain nothing on 2048^2: the
-// same 37-row segments measure the same, and the shorter segments that fill
-// three slots per CU are slower (25 rows in one round: 130.6 against 125.6
-// us per launch), the pass being bound by the HBM access pattern rather than
-// by latency.  The FP32-arithmetic modes fit four.
+// Waves per SIMD the two-step pass is compiled for.  FP64 runs at two (186
+// VGPRs with BGK and the force, 38 kB of LDS per workgroup).  An earlier form
+// of the pass was made to fit three (168 VGPRs with the density summed again
+// at the collision and a few loop-invariant reloads) and gained nothing on
+// 2048^2: the same 37-row segments measured the same, and the shorter
+// segments that fill three slots per CU were slower (25 rows in one round:
+// 130.6 against 125.6 us per launch), the pass being bound by the HBM access
+// pattern rather than by latency.  The FP32-arithmetic modes fit four.
 template <int ST>
 constexpr int kWaves2 = ST == LBM_STORE_F64 ? 2 : 4;
 
