@@ -87,9 +87,10 @@ TEMPS = (0.6, 0.7, 0.8, 0.9)
 WARMUP_FLOOR_STEPS = 200      # untimed steps before any timed region
 # Launch shape (threads per workgroup, segment rows) of the four-lattice batch
 # per steps per launch and storage mode: the fastest of `--launch` sweeps of
-# this workload (two-step pass: FP64 rows 24/32/37 gave 70.5/72.3/71.6 G
-# cell updates/s; FP32 12..20 rows 136, 37 rows 130; FP16 37 rows 183, 24 rows
-# 174; per-cell FP16 32 and 37 rows 134.5, 24 rows 129).  Fixed, so that runs
+# this workload (two-step pass, G cell updates/s: FP64 rows 24/32/37/48 gave
+# 71.2/72.7/71.8/66.9; FP32 rows 12/16/21 137.2/136.6/136.1, within run-to-run
+# noise; FP16 rows 24/30/37/48 176.7/181.5/185.1/169.1; per-cell FP16 the same
+# rows 136.6/140.6/142.9/131.9).  Fixed, so that runs
 # are reproducible and launch the shape the committed counters were taken on;
 # --autotune times the candidates instead (lbm_batch_autotune), which cannot
 # tell shapes 1% apart from run to run.
